@@ -1,0 +1,414 @@
+"""Pins of the FP64 oracle to what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values
+printed in the paper (golden fixtures), textbook constants, closed-form
+solutions, exact invariants, and brute-force permutations.  A plausible
+mistake in the oracle (a wrong velocity entry, a dropped or mis-signed term,
+a wrong viscosity relation, a transposed index) fails at least one of them.
+"""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+Q = 19
+
+
+def _E():
+    return oracle.velocities().astype(np.float64)
+
+
+def _eq_linear(u):
+    """Populations w (1 + 3 e.u) with the given velocity field (3, nz, ny, nx):
+    a first-order-accurate start that the collision relaxes within a few steps."""
+    E, w = _E(), oracle.weights()
+    return w[:, None, None, None] * (1.0 + 3.0 * np.einsum("ad,d...->a...", E, u))
+
+
+def _K_from_definition(E):
+    """The orthogonal basis K_0..K_18 of Sec. 3, evaluated on the velocity set."""
+    ex, ey, ez = E[:, 0], E[:, 1], E[:, 2]
+    sq = ex ** 2 + ey ** 2 + ez ** 2
+    one = np.ones(Q)
+    cols = [one, ex, ey, ez, ex * ey, ex * ez, ey * ez, ex ** 2 - ey ** 2, sq - 3 * ez ** 2,
+            19 * sq - 30 * one, 5 * ex * sq - 9 * ex, 5 * ey * sq - 9 * ey, 5 * ez * sq - 9 * ez,
+            ex * ey ** 2 - ex * ez ** 2, ez ** 2 * ey - ey * ex ** 2, ex ** 2 * ez - ey ** 2 * ez,
+            21 * (ex ** 2 * ey ** 2 + ex ** 2 * ez ** 2 + ey ** 2 * ez ** 2) - 16 * sq + 12 * one,
+            3 * (ex ** 2 * ey ** 2 + ex ** 2 * ez ** 2 - 2 * ey ** 2 * ez ** 2)
+            - 2 * (2 * ex ** 2 - ey ** 2 - ez ** 2),
+            3 * (ex ** 2 * ey ** 2 - ex ** 2 * ez ** 2) - 2 * (ey ** 2 - ez ** 2)]
+    return np.stack(cols, axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Lattice tables
+# ---------------------------------------------------------------------------
+
+def test_velocities_match_printed_components():
+    printed = np.loadtxt(os.path.join(GOLDEN, "paper_velocity_components.txt"))
+    assert np.array_equal(_E().T, printed)
+
+
+def test_K_from_oracle_velocities_matches_printed_matrix():
+    """K rebuilt from its definition on the oracle's velocities equals the
+    printed matrix in every entry but one: row alpha = 15, column K_14."""
+    printed = np.loadtxt(os.path.join(GOLDEN, "paper_K_matrix.txt"))
+    K = _K_from_definition(_E())
+    diff = np.argwhere(K != printed)
+    assert diff.tolist() == [[15, 14]]
+    assert printed[15, 14] == -1 and K[15, 14] == 1
+
+
+def test_K_definition_is_orthogonal():
+    K = _K_from_definition(_E())
+    G = K.T @ K
+    assert np.array_equal(G, np.diag(np.diag(G)))
+    assert np.diag(G).tolist() == [19, 10, 10, 10, 4, 4, 4, 12, 36, 2394, 40, 40, 40, 8, 8, 8,
+                                   252, 72, 24]
+    printed = np.loadtxt(os.path.join(GOLDEN, "paper_K_matrix.txt"))
+    Gp = printed.T @ printed
+    assert Gp[14, 15] != 0          # the printed sign breaks orthogonality
+
+
+def test_weights_are_textbook_d3q19():
+    with open(os.path.join(GOLDEN, "d3q19_weights.txt")) as fh:
+        vals = [float(Fraction(l.strip())) for l in fh if l.strip() and not l.startswith("#")]
+    # the oracle derives them by a linear solve: equal up to a few ulp
+    assert np.allclose(oracle.weights(), vals, rtol=0, atol=1e-15)
+
+
+def test_opposites():
+    E, opp = _E(), oracle.opposite()
+    assert np.array_equal(E[opp], -E)
+
+
+# ---------------------------------------------------------------------------
+# Collision invariants
+# ---------------------------------------------------------------------------
+
+def _random_state(rng, amp=0.02, u=(0.03, -0.02, 0.01)):
+    E, w = _E(), oracle.weights()
+    f = w * (1.0 + 3.0 * E @ np.array(u)) * (1.0 + amp * rng.uniform(-1, 1, Q))
+    return f
+
+
+@pytest.mark.parametrize("n", [0.5, 1.0, 1.5])
+@pytest.mark.parametrize("force", [(0.0, 0.0, 0.0), (1e-4, -2e-4, 3e-5)])
+def test_collision_conserves_mass_and_momentum(n, force):
+    rng = np.random.default_rng(7)
+    E = _E()
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.02, n=n, force=force)
+    for _ in range(20):
+        f = _random_state(rng)
+        ft, _ = oracle.collide_node(spec, f)
+        assert abs(ft.sum() - f.sum()) <= 2e-16 * f.sum() * 4
+        assert np.allclose(E.T @ ft, E.T @ f + np.array(force), rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("n", [0.4, 0.75, 1.0, 1.6])
+def test_rest_state_is_invariant(n):
+    w = oracle.weights()
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.01, n=n)
+    ft, _ = oracle.collide_node(spec, w)
+    assert np.abs(ft - w).max() <= 1e-16
+
+
+@pytest.mark.parametrize("rho0", [0.97, 1.05])
+def test_equilibrium_is_density_homogeneous(rho0):
+    """With the density-normalized fourth-order attractor the rest
+    equilibrium scales with rho: C(rho w) = rho w."""
+    w = oracle.weights()
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.01, n=0.8)
+    ft, _ = oracle.collide_node(spec, rho0 * w)
+    assert np.abs(ft - rho0 * w).max() <= 4e-16
+
+
+@pytest.mark.parametrize("literal", [0, 1])
+def test_fourth_order_attractor_reading(literal):
+    """The fourth-order attractor printed without 1/rho (Sec. 3) makes a
+    periodic box unstable to a 1e-4 density perturbation at omega = 1.25; the
+    density-normalized product (Maxwellian value c_s^4 rho at equilibrium)
+    damps it.  This is the evidence for the reading used throughout."""
+    spec = W.LatticeSpec(nx=6, ny=6, nz=6, K=0.1, n=1.0, periodic=(1, 1, 1),
+                         attractor_literal=literal)
+    w = oracle.weights()[:, None, None, None]
+    f = W.perturbed_populations(spec, 1, eps=1e-4).numpy()
+    d0 = np.abs(f - w).max()
+    f = oracle.run(spec, f, 40)
+    d1 = np.abs(f - w).max()
+    if literal:
+        assert not (d1 < 10 * d0)          # grows by orders of magnitude (or overflows)
+    else:
+        assert d1 < d0
+
+
+def test_unit_relaxation_is_idempotent():
+    """With every relaxation rate equal to one (n = 1, K = 1/6 gives omega = 1 at
+    rho = 1) a collision lands on the attractor; a second one changes nothing."""
+    rng = np.random.default_rng(3)
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=1.0 / 6.0, n=1.0)
+    for _ in range(5):
+        f = _random_state(rng)
+        f = f / f.sum()
+        ft, om = oracle.collide_node(spec, f)
+        assert abs(om - 1.0) < 1e-15
+        ftt, _ = oracle.collide_node(spec, ft)
+        assert np.abs(ftt - ft).max() < 1e-15
+
+
+def _signed_permutations():
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            P = np.zeros((3, 3))
+            for i, (j, s) in enumerate(zip(perm, signs)):
+                P[i, j] = s
+            yield P
+
+
+@pytest.mark.parametrize("n", [0.6, 1.4])
+def test_collision_commutes_with_cube_symmetries(n):
+    """All second-order rates are equal and the higher ones are one, so the
+    collision is isotropic: it commutes with the 48 rotations/reflections of
+    the cube, which act on populations by permuting the velocity index."""
+    E = _E()
+    rng = np.random.default_rng(11)
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.01, n=n)
+    f = _random_state(rng, amp=0.05)
+    ft, _ = oracle.collide_node(spec, f)
+    count = 0
+    for P in _signed_permutations():
+        PE = E @ P.T
+        pi = np.array([np.flatnonzero((E == PE[a]).all(axis=1))[0] for a in range(Q)])
+        g = np.empty(Q)
+        g[pi] = f                     # population moving along e_a moves along P e_a
+        gt, _ = oracle.collide_node(spec, g)
+        expect = np.empty(Q)
+        expect[pi] = ft
+        assert np.abs(gt - expect).max() < 2e-15
+        count += 1
+    assert count == 48
+
+
+# ---------------------------------------------------------------------------
+# Local relaxation rate: closed forms of the implicit equation
+# ---------------------------------------------------------------------------
+
+def _pure_shear_state(m4):
+    """rho = 1, u = 0 and a single non-equilibrium moment m4 = kappa'_xy."""
+    f = oracle.weights().copy()
+    eps = m4 / 4.0
+    f[7] += eps; f[10] += eps; f[8] -= eps; f[9] -= eps
+    return f
+
+
+def _pure_dilatation_state(m9):
+    """rho = 1, u = 0 and only the trace moment away from equilibrium."""
+    f = oracle.weights().copy()
+    eps = m9 / 6.0
+    f[1:7] += eps
+    f[0] -= 6 * eps
+    return f
+
+
+@pytest.mark.parametrize("m4", [1e-4, 3e-3])
+def test_omega_closed_form_shear_thinning_half(m4):
+    """n = 1/2, pure shear: |gamma| = 3 omega |m4| (Eq. strain rate tensor and
+    Eq. shear rate), so tau - 1/2 = 3 K (3|m4|)^(-1/2) tau^(1/2): a quadratic in
+    sqrt(tau)."""
+    K = 2e-3
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=K, n=0.5)
+    _, om = oracle.collide_node(spec, _pure_shear_state(m4))
+    c = 3 * K * (3 * m4) ** -0.5
+    s = (c + np.sqrt(c * c + 2)) / 2
+    assert om == pytest.approx(1 / s ** 2, rel=1e-14)
+
+
+def test_omega_closed_form_newtonian():
+    rng = np.random.default_rng(5)
+    for K in (0.01, 0.1, 0.5):
+        spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=K, n=1.0)
+        f = _random_state(rng)
+        f *= 1.07
+        _, om = oracle.collide_node(spec, f)
+        assert om == pytest.approx(1 / (3 * K / f.sum() + 0.5), rel=1e-15)
+
+
+@pytest.mark.parametrize("m4", [2e-4, 5e-3])
+def test_omega_closed_form_shear_thickening(m4):
+    """n = 2: tau - 1/2 = 3 K * 3 |m4| / tau, a quadratic in tau;
+    n = 3/2: s^3 - s/2 - 3 K sqrt(3 |m4|) = 0 with s = sqrt(tau) (numpy roots)."""
+    K = 5.0
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=K, n=2.0)
+    _, om = oracle.collide_node(spec, _pure_shear_state(m4))
+    tau = (0.5 + np.sqrt(0.25 + 36 * K * m4)) / 2
+    assert om == pytest.approx(1 / tau, rel=1e-14)
+    K = 2.0
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=K, n=1.5)
+    _, om = oracle.collide_node(spec, _pure_shear_state(m4))
+    roots = np.roots([1.0, 0.0, -0.5, -3 * K * np.sqrt(3 * m4)])
+    s = max(r.real for r in roots if abs(r.imag) < 1e-12)
+    assert om == pytest.approx(1 / s ** 2, rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [0.5, 1.5])
+def test_omega_closed_form_pure_dilatation(n):
+    """Only m9: S = q I with q = -omega_9 m9 / 2, |gamma| = sqrt(6)|q| does not
+    depend on omega^nu, so omega^nu = 1/(3 K |gamma|^(n-1) + 1/2)."""
+    K, m9 = 0.01 if n < 1 else 0.2, 4e-3
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=K, n=n)
+    _, om = oracle.collide_node(spec, _pure_dilatation_state(m9))
+    g = np.sqrt(6.0) * m9 / 2
+    assert om == pytest.approx(1 / (3 * K * g ** (n - 1) + 0.5), rel=1e-14)
+
+
+def test_omega_clip_limits():
+    # shear thinning with vanishing shear -> viscosity clipped at nu_max
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=1e-3, n=0.5)
+    _, om = oracle.collide_node(spec, oracle.weights())
+    assert om == pytest.approx(1 / (3 * spec.nu_max + 0.5), rel=1e-15)
+    # shear thickening with vanishing shear -> nu_min
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=1e-3, n=1.5)
+    _, om = oracle.collide_node(spec, oracle.weights())
+    assert om == pytest.approx(1 / (3 * spec.nu_min + 0.5), rel=1e-15)
+    # huge consistency -> nu_max even under shear
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=1e3, n=0.5)
+    _, om = oracle.collide_node(spec, _pure_shear_state(1e-3))
+    assert om == pytest.approx(1 / (3 * spec.nu_max + 0.5), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Streaming and boundaries
+# ---------------------------------------------------------------------------
+
+def test_periodic_streaming_is_a_shift():
+    E = _E().astype(int)
+    spec = W.LatticeSpec(nx=5, ny=4, nz=3, K=0.01, n=1.0, periodic=(1, 1, 1))
+    rng = np.random.default_rng(0)
+    ft = rng.uniform(size=(Q, 3, 4, 5))
+    f = oracle.stream(spec, ft)
+    for a in range(Q):
+        ex, ey, ez = E[a]
+        assert np.array_equal(f[a], np.roll(ft[a], shift=(ez, ey, ex), axis=(0, 1, 2)))
+
+
+def test_resting_walls_permute_values():
+    """With stationary walls streaming only moves values around: every value
+    arrives at exactly one place."""
+    spec = W.LatticeSpec(nx=4, ny=5, nz=3, K=0.01, n=1.0, periodic=(0, 1, 0))
+    rng = np.random.default_rng(1)
+    ft = rng.uniform(size=(Q, 3, 5, 4))
+    f = oracle.stream(spec, ft)
+    assert np.array_equal(np.sort(f.ravel()), np.sort(ft.ravel()))
+
+
+def test_cavity_mass_and_mirror_symmetry():
+    """Closed lid-driven cavity: the lid momentum terms cancel pairwise at each
+    top node, so total mass is conserved; the flow is mirror-symmetric about
+    the mid-plane normal to z (u_z odd, u_x and u_y even)."""
+    U = 0.05
+    spec = W.cavity(10, U, 0.7, 50.0)
+    assert spec.attractor_literal == 0
+    f = oracle.run(spec, W.rest_populations(spec).numpy(), 60)
+    rho, u = oracle.macroscopic(spec, f)
+    assert abs(rho.sum() - spec.nodes) <= 1e-12 * spec.nodes
+    zflip = u[:, ::-1, :, :]
+    assert np.abs(u[0] - zflip[0]).max() < 1e-14
+    assert np.abs(u[1] - zflip[1]).max() < 1e-14
+    assert np.abs(u[2] + zflip[2]).max() < 1e-14
+    assert np.abs(u[0]).max() > 0.1 * U
+
+
+# ---------------------------------------------------------------------------
+# Flows with closed-form solutions
+# ---------------------------------------------------------------------------
+
+def _couette(n, U, H=8, steps=8000):
+    g = U / H
+    K = 0.1 / g ** (n - 1)
+    spec = W.LatticeSpec(nx=1, ny=H, nz=1, K=K, n=n, periodic=(1, 0, 1), lid_face=W.LID_PY,
+                         lid_velocity=(U, 0.0, 0.0))
+    y = np.arange(H)
+    u = np.zeros((3, 1, H, 1))
+    u[0, 0, :, 0] = U * (y + 0.5) / H
+    f = oracle.run(spec, _eq_linear(u), steps)
+    _, uu = oracle.macroscopic(spec, f)
+    _, om = oracle.collide(spec, f, with_omega=True)
+    om_exact = 1 / (3 * K * g ** (n - 1) + 0.5)
+    uerr = np.abs(uu[0, 0, :, 0] - U * (y + 0.5) / H).max() / U
+    return uerr, np.abs(om - om_exact).max() / om_exact
+
+
+@pytest.mark.parametrize("n", [0.5, 1.5])
+def test_power_law_couette(n):
+    """Plate moving at U over H nodes (Eqs. 5-6): the exact steady solution is
+    linear with uniform |gamma| = U/H, hence uniform omega^nu =
+    1/(3 K (U/H)^(n-1) + 1/2).  This pins the strain-rate estimate, the
+    power-law viscosity and the moving-wall term.  The weakly compressible
+    scheme leaves an O(U^2) (Mach-squared) remainder: it must shrink by 4 when
+    U halves, and stay below 0.05 U^2 (velocity) and 0.1 U^2 (omega)."""
+    e1u, e1o = _couette(n, 0.02)
+    e2u, e2o = _couette(n, 0.01)
+    assert e1u < 0.05 * 0.02 ** 2 and e1o < 0.1 * 0.02 ** 2
+    assert e2u < 0.05 * 0.01 ** 2 and e2o < 0.1 * 0.01 ** 2
+    assert 3.5 < e1u / e2u < 4.5 and 3.5 < e1o / e2o < 4.5
+
+
+def test_shear_wave_decay_gives_newtonian_viscosity():
+    """n = 1: a transverse shear wave decays as exp(-nu k^2 t) with
+    nu = c_s^2 (1/omega - 1/2) (Sec. 3.1).  A 64-node period keeps the
+    lattice correction to the decay rate well under 1e-3."""
+    L, U0, K = 64, 1e-3, 0.05
+    spec = W.LatticeSpec(nx=1, ny=L, nz=1, K=K, n=1.0, periodic=(1, 1, 1))
+    k = 2 * np.pi / L
+    y = np.arange(L)
+    u = np.zeros((3, 1, L, 1))
+    u[0, 0, :, 0] = U0 * np.sin(k * y)
+    f = oracle.run(spec, _eq_linear(u), 20)
+
+    def amp(f):
+        _, uu = oracle.macroscopic(spec, f)
+        return (uu[0, 0, :, 0] * np.sin(k * y)).sum() / (np.sin(k * y) ** 2).sum()
+
+    a0 = amp(f)
+    T = 400
+    f = oracle.run(spec, f, T)
+    rate = np.log(a0 / amp(f)) / T
+    assert rate == pytest.approx(K * k * k, rel=1e-3)
+
+
+def _poiseuille_l2(n, H, umax=None, Re=10.0, tol=1e-7, chunk=2000, maxsteps=400000):
+    umax = 0.08 / H if umax is None else umax
+    spec = W.poiseuille(1, H, 1, n=n, Re=Re, umax=umax)
+    K, F = spec.K, spec.force[0]
+    y = np.arange(H) - (H - 1) / 2
+    ua = n / (n + 1) * (F / K) ** (1 / n) * ((H / 2) ** ((n + 1) / n) - np.abs(y) ** ((n + 1) / n))
+    u = np.zeros((3, 1, H, 1))
+    u[0, 0, :, 0] = ua
+    f = _eq_linear(u)
+    prev, steps = None, 0
+    while steps < maxsteps:
+        f = oracle.run(spec, f, chunk)
+        steps += chunk
+        _, uu = oracle.macroscopic(spec, f)
+        if prev is not None and np.abs(uu[0] - prev).max() / umax < tol:
+            break
+        prev = uu[0].copy()
+    return np.sqrt(((uu[0, 0, :, 0] - ua) ** 2).sum() / (ua ** 2).sum())
+
+
+@pytest.mark.parametrize("n", [0.5, 0.8, 1.0, 1.5])
+def test_poiseuille_closed_form_second_order(n):
+    """Power-law channel (Sec. 4.1): the steady profile approaches the closed
+    form u(y) = n/(n+1) (F/K)^(1/n) [(H/2)^((n+1)/n) - |y|^((n+1)/n)] with order 2
+    under diffusive scaling (u_max ~ 1/H, Re fixed), as the paper reports."""
+    e8 = _poiseuille_l2(n, 8)
+    e16 = _poiseuille_l2(n, 16)
+    assert e16 < 0.01
+    order = np.log2(e8 / e16)
+    assert 1.8 < order < 2.2
