@@ -1,0 +1,170 @@
+/*
+ * clbm.h — D3Q19 cascaded (central-moment, multiple-relaxation-time) lattice
+ * Boltzmann method for power-law fluids on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Adam, Hajabdollahi & Premnath, "Cascaded lattice Boltzmann modeling
+ * and simulations of three-dimensional non-Newtonian fluid flows",
+ * arXiv:1908.05396.  Section numbers below refer to that paper.
+ *
+ * One time step (Sec. 3) is: collide every node (central moments about the
+ * local velocity, second-order rates set from the local shear rate through
+ * the power-law viscosity, higher orders relaxed to factorized attractors),
+ * then stream (Eq. cascaded streaming).  The library fuses both into one pull
+ * kernel: each node gathers the post-collision populations of its upwind
+ * neighbours, applies the wall rules, collides and writes its own
+ * post-collision populations to the other of two buffers.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, c_s^2 = 1/3, rest density 1.
+ *   - Particle velocities e_alpha, alpha = 0..18, in the order of Sec. 3:
+ *     rest; +x -x +y -y +z -z; (+1,+1,0) (-1,+1,0) (+1,-1,0) (-1,-1,0);
+ *     (+1,0,+1) (-1,0,+1) (+1,0,-1) (-1,0,-1); (0,+1,+1) (0,-1,+1) (0,+1,-1)
+ *     (0,-1,-1).
+ *   - Node index i = x + nx*(y + ny*z) (x fastest).  Walls are not stored:
+ *     they sit half-way between the outermost fluid node and a virtual ghost
+ *     layer (half-way bounce-back, Sec. 4.1).
+ *   - State buffers hold, for each alpha, a plane of `plane_stride` values
+ *     (>= nx*ny*nz, padded), structure of arrays: value(alpha, i) at
+ *     element alpha*plane_stride + i.  Each value is the deviation
+ *     f_alpha - w_alpha of the post-collision population from the rest
+ *     weight w = (1/3, 1/18 x 6, 1/36 x 12), stored as double (CLBM_F64),
+ *     float (CLBM_F32) or IEEE half (CLBM_F16_DEV, round to nearest even).
+ *     Arithmetic is double for CLBM_F64 and float otherwise.
+ *   - All device pointers must be 256-byte aligned device memory owned by
+ *     the caller.  The library never frees caller memory.  It allocates a
+ *     small amount of its own device memory in clbm_create (reduction
+ *     partials, an optional velocity snapshot) and none in clbm_step.
+ *   - Streams are hipStream_t values passed as void* (0 = null stream).
+ *     clbm_step and the other launches are asynchronous; clbm_reduce
+ *     synchronizes its stream.
+ *   - Every function returns clbm_status; on failure clbm_last_error()
+ *     returns a message (thread-local).  A handle must be used from one host
+ *     thread at a time.
+ */
+#ifndef CLBM_H
+#define CLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CLBM_OK = 0,
+    CLBM_EINVAL = -1,    /* bad argument or parameter */
+    CLBM_ENOMEM = -2,    /* library-side allocation failed */
+    CLBM_EHIP = -3,      /* a HIP runtime call failed */
+    CLBM_EUNSTABLE = -4, /* clbm_reduce found NaN/Inf in the state */
+    CLBM_ESTATE = -5     /* call out of order (e.g. step before init) */
+} clbm_status;
+
+typedef enum {
+    CLBM_F64 = 0,     /* FP64 storage, FP64 arithmetic */
+    CLBM_F32 = 1,     /* FP32 storage of f - w, FP32 arithmetic */
+    CLBM_F16_DEV = 2  /* FP16 storage of f - w, FP32 arithmetic */
+} clbm_storage;
+
+typedef enum {
+    CLBM_LID_NONE = 0, CLBM_LID_MX = 1, CLBM_LID_PX = 2, CLBM_LID_MY = 3,
+    CLBM_LID_PY = 4, CLBM_LID_MZ = 5, CLBM_LID_PZ = 6
+} clbm_lid_face;
+
+/* Problem description (Sec. 2 constitutive law, Sec. 3 scheme, Sec. 4 set-ups).
+ * Fill with clbm_params_default() and override. */
+typedef struct {
+    int32_t nx, ny, nz;        /* fluid nodes per axis (each >= 1) */
+    int32_t periodic[3];       /* 1: periodic axis; 0: half-way bounce-back walls at both ends */
+    int32_t lid_face;          /* clbm_lid_face: the wall whose ghost plane moves with lid_velocity
+                                  (edge and corner ghosts of that plane included) */
+    int32_t storage;           /* clbm_storage */
+    int32_t attractor_literal; /* 0: fourth-order attractors kxx*kyy/rho (default);
+                                  1: kxx*kyy as printed (linearly unstable, for study only) */
+    int32_t track_residual;    /* 1: keep a velocity snapshot for the steady-state residual */
+    double K;                  /* consistency coefficient mu_p > 0 (Eq. 5) */
+    double n;                  /* power-law index n > 0 (Eq. 5; n = 1 Newtonian) */
+    double nu_min, nu_max;     /* clip of the apparent kinematic viscosity mu/rho,
+                                  0 < nu_min < nu_max */
+    double omega_bulk;         /* omega_9 in (0, 2); the paper uses 1 */
+    double omega_high[9];      /* omega_10 .. omega_18 in (0, 2); the paper uses 1 */
+    double force[3];           /* body force per unit volume (0: unforced kernel) */
+    double lid_velocity[3];    /* velocity U_w of the moving wall */
+    double rho_wall;           /* density in the moving-wall term 2 w rho_w (e.U_w)/c_s^2, > 0 */
+} clbm_params;
+
+typedef struct clbm_lattice clbm_lattice;
+
+/* Defaults: 1x1x1, no periodic axis, no lid, FP32 storage, normalized
+ * attractors, residual tracking on, K = 0.01, n = 1, viscosity clip for
+ * omega in [0.1, 1.99], omega_bulk = omega_high = 1, no force, rho_wall = 1. */
+clbm_status clbm_params_default(clbm_params *p);
+
+/* Elements per population plane for these dimensions and storage (padded so
+ * every plane starts 256-byte aligned), and the bytes one state buffer needs
+ * (19 planes).  Either output pointer may be NULL. */
+clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane_stride, size_t *bytes);
+
+/* Create a lattice over two caller-owned state buffers of `bytes_each` bytes
+ * (>= clbm_buffer_size), 256-byte aligned.  Validates every parameter
+ * (EINVAL), allocates reduction scratch (ENOMEM/EHIP).  The state is
+ * undefined until an init call. */
+clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each,
+                        clbm_lattice **out);
+
+/* Rest initial state f = w (rho = 1, u = 0), collided once so the buffer
+ * holds post-collision populations (time 0). */
+clbm_status clbm_init_rest(clbm_lattice *h, void *stream);
+
+/* Initial state from caller populations f0 (device memory, double, 19
+ * planes of nx*ny*nz values, unpadded, alpha-major): collided once and stored
+ * in the state's format.  f0 is only read. */
+clbm_status clbm_init_populations(clbm_lattice *h, const double *f0_dev, void *stream);
+
+/* Advance nsteps time steps (>= 0): one fused pull stream-collide launch per
+ * step.  Asynchronous; no host synchronization. */
+clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream);
+
+/* Density and velocity at the current time (device outputs, double,
+ * unpadded): rho[i], u[c*N + i] for c = x, y, z.  Collision conserves mass
+ * and momentum, so they are read from the stored post-collision populations:
+ * rho = sum f, u = (sum e f - F/2)/rho.  Either pointer may be NULL. */
+clbm_status clbm_macroscopic(clbm_lattice *h, double *rho_dev, double *u_dev, void *stream);
+
+/* Post-collision populations f = w + stored deviation, as double, 19 unpadded
+ * planes (device output). */
+clbm_status clbm_populations(clbm_lattice *h, double *f_dev, void *stream);
+
+/* FP64 reductions over the lattice (synchronizes `stream`):
+ *   out[0] total mass sum rho          out[4] residual |u - u_prev|_2 / |u|_2
+ *   out[1..3] total momentum sum rho u     against the previous clbm_reduce
+ *                                          (0 on the first call or if untracked)
+ *   out[5] number of nodes with non-finite populations
+ *   out[6] max |u|                     out[7] kinetic energy sum rho |u|^2 / 2
+ * Returns CLBM_EUNSTABLE (after filling out) if out[5] > 0. */
+clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream);
+
+/* Index (0 = pop_a, 1 = pop_b) of the buffer holding the current state, and
+ * the number of steps taken since the last init. */
+clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done);
+
+/* Launch shape of the stream-collide kernel: threads per block along x and y
+ * (bx*by in {64,...,1024}, bx a multiple of 64 or equal to nx).  Used by the
+ * autotuner; the default is chosen at create. */
+clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by);
+clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by);
+
+clbm_status clbm_destroy(clbm_lattice *h);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *clbm_last_error(void);
+
+/* Version string and the lattice tables compiled into the kernels (for
+ * tests): e[3*alpha + c], opposite[alpha], w[alpha]. */
+const char *clbm_version(void);
+clbm_status clbm_lattice_tables(int32_t *e, int32_t *opposite, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLBM_H */

@@ -32,8 +32,10 @@
  *      Sec. 3.  The paper prints the product without 1/rho; that form is
  *      available with attractor_literal = 1, but it makes the scheme
  *      linearly unstable to density perturbations (equal at rho = 1).
- *   6. post-collision populations: the unique f~ whose central moments are
- *      the relaxed ones (linear solve with the per-node moment matrix)
+ *   6. post-collision populations f~ = f + Omega (Eq. cascaded collision):
+ *      Omega is the unique population change whose central moments equal
+ *      the relaxed minus the incoming ones (linear solve with the per-node
+ *      moment matrix)
  *   7. streaming f(x + e, t+1) = f~(x, t) (Eq. cascaded streaming) with
  *      periodic axes, half-way bounce-back walls and a moving-lid momentum
  *      correction (Sec. 4.1, 4.2, 4.3).
@@ -351,8 +353,15 @@ int orc_collide_node(const orc_params *p, const double *fin, double *fout, doubl
         kt[r] = s;
     }
 
-    /* post-collision populations with exactly these central moments */
-    if (populations_from_central(u, kt, fout)) return -1;
+    /* post-collision populations: f~ = f + Omega (Eq. cascaded collision),
+     * with Omega the unique change of populations whose central moments
+     * change by kappa~ - kappa.  Solving for the (small) change rather than
+     * for f~ itself keeps the linear solve's rounding proportional to the
+     * change. */
+    double dk[Q], df[Q];
+    for (int r = 0; r < Q; ++r) dk[r] = kt[r] - kap[r];
+    if (populations_from_central(u, dk, df)) return -1;
+    for (int a = 0; a < Q; ++a) fout[a] = f[a] + df[a];
     if (forced)
         for (int a = 0; a < Q; ++a) fout[a] += 0.5 * S[a];
     return 0;

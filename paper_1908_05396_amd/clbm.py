@@ -1,0 +1,242 @@
+"""ctypes binding of libclbm.so (the C-ABI declared in include/clbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch provides device memory and streams.  If the library
+is not built, importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libclbm.so")
+
+Q = 19
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+STORAGE_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
+
+CLBM_OK, CLBM_EINVAL, CLBM_ENOMEM, CLBM_EHIP, CLBM_EUNSTABLE, CLBM_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class ClbmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"clbm error {status}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3),
+        ("lid_face", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("attractor_literal", ctypes.c_int32),
+        ("track_residual", ctypes.c_int32),
+        ("K", ctypes.c_double), ("n", ctypes.c_double),
+        ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double),
+        ("omega_high", ctypes.c_double * 9),
+        ("force", ctypes.c_double * 3),
+        ("lid_velocity", ctypes.c_double * 3),
+        ("rho_wall", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+#: every function the header declares, with (restype, argtypes)
+_VP, _DP, _I32P, _I64P = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), \
+    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+_PP = ctypes.POINTER(Params)
+SIGNATURES = {
+    "clbm_params_default": (ctypes.c_int, [_PP]),
+    "clbm_buffer_size": (ctypes.c_int, [_PP, _I64P, ctypes.POINTER(ctypes.c_size_t)]),
+    "clbm_create": (ctypes.c_int, [_PP, _VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    "clbm_init_rest": (ctypes.c_int, [_VP, _VP]),
+    "clbm_init_populations": (ctypes.c_int, [_VP, _VP, _VP]),
+    "clbm_step": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
+    "clbm_macroscopic": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "clbm_populations": (ctypes.c_int, [_VP, _VP, _VP]),
+    "clbm_reduce": (ctypes.c_int, [_VP, _DP, _VP]),
+    "clbm_state": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int), _I64P]),
+    "clbm_set_block": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "clbm_get_block": (ctypes.c_int, [_VP, _I32P, _I32P]),
+    "clbm_destroy": (ctypes.c_int, [_VP]),
+    "clbm_last_error": (ctypes.c_char_p, []),
+    "clbm_version": (ctypes.c_char_p, []),
+    "clbm_lattice_tables": (ctypes.c_int, [_I32P, _I32P, _DP]),
+}
+
+
+def load():
+    """Load libclbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is not built; run __graft_entry__.build() "
+                          "(python -m paper_1908_05396_amd.build)")
+    lib = ctypes.CDLL(LIBPATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != CLBM_OK:
+        raise ClbmError(rc, load().clbm_last_error().decode())
+
+
+def version() -> str:
+    return load().clbm_version().decode()
+
+
+def lattice_tables():
+    """(e[19,3], opposite[19], w[19]) compiled into the kernels."""
+    import numpy as np
+    e = (ctypes.c_int32 * (3 * Q))()
+    o = (ctypes.c_int32 * Q)()
+    w = (ctypes.c_double * Q)()
+    _check(load().clbm_lattice_tables(e, o, w))
+    return (np.array(list(e), dtype=np.int64).reshape(Q, 3), np.array(list(o)), np.array(list(w)))
+
+
+def params_from_spec(spec, storage: str = "f32", track_residual: bool = True) -> Params:
+    """Fill the C parameter struct from a problem description with the
+    attributes of workloads.LatticeSpec."""
+    p = Params()
+    _check(load().clbm_params_default(ctypes.byref(p)))
+    p.nx, p.ny, p.nz = int(spec.nx), int(spec.ny), int(spec.nz)
+    for d in range(3):
+        p.periodic[d] = 1 if spec.periodic[d] else 0
+        p.force[d] = float(spec.force[d])
+        p.lid_velocity[d] = float(spec.lid_velocity[d])
+    p.lid_face = int(spec.lid_face)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.attractor_literal = int(getattr(spec, "attractor_literal", 0))
+    p.track_residual = 1 if track_residual else 0
+    p.K, p.n = float(spec.K), float(spec.n)
+    p.nu_min, p.nu_max = float(spec.nu_min), float(spec.nu_max)
+    p.omega_bulk = float(spec.omega_bulk)
+    for k in range(9):
+        p.omega_high[k] = float(spec.omega_high[k])
+    p.rho_wall = float(spec.rho_wall)
+    return p
+
+
+def buffer_size(p: Params):
+    plane = ctypes.c_int64()
+    nbytes = ctypes.c_size_t()
+    _check(load().clbm_buffer_size(ctypes.byref(p), ctypes.byref(plane), ctypes.byref(nbytes)))
+    return int(plane.value), int(nbytes.value)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Lattice:
+    """One lattice on one GPU: two state buffers owned by torch, a library
+    handle, and thin wrappers of the C calls."""
+
+    def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
+                 block=None):
+        lib = load()
+        self.spec = spec
+        self.storage = storage
+        self.params = params_from_spec(spec, storage, track_residual)
+        self.plane, self.nbytes = buffer_size(self.params)
+        self.device = torch.device(device)
+        self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        h = ctypes.c_void_p()
+        _check(lib.clbm_create(ctypes.byref(self.params), ctypes.c_void_p(self.buffers[0].data_ptr()),
+                               ctypes.c_void_p(self.buffers[1].data_ptr()), ctypes.c_size_t(self.nbytes),
+                               ctypes.byref(h)))
+        self._h = h
+        if block is not None:
+            self.set_block(*block)
+
+    @property
+    def nodes(self) -> int:
+        return self.params.nx * self.params.ny * self.params.nz
+
+    @property
+    def shape(self):
+        return (self.params.nz, self.params.ny, self.params.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().clbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state -------------------------------------------------------------
+    def init_rest(self, stream=None):
+        _check(load().clbm_init_rest(self._h, _stream(stream)))
+
+    def init_populations(self, f0: torch.Tensor, stream=None):
+        """f0: float64 device tensor of shape (19, nz, ny, nx)."""
+        f0 = f0.to(device=self.device, dtype=torch.float64).contiguous()
+        assert f0.numel() == Q * self.nodes, "f0 must hold 19 x nx*ny*nz values"
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(load().clbm_init_populations(self._h, ctypes.c_void_p(f0.data_ptr()), _stream(s)))
+        if s != torch.cuda.current_stream(self.device):
+            f0.record_stream(s)     # the launch may still read f0 after this returns
+
+    def step(self, nsteps: int, stream=None):
+        _check(load().clbm_step(self._h, int(nsteps), _stream(stream)))
+
+    def state(self):
+        idx = ctypes.c_int()
+        steps = ctypes.c_int64()
+        _check(load().clbm_state(self._h, ctypes.byref(idx), ctypes.byref(steps)))
+        return idx.value, steps.value
+
+    def state_tensor(self) -> torch.Tensor:
+        """The current state buffer as (19, plane_stride) deviations f - w."""
+        idx, _ = self.state()
+        dt = STORAGE_DTYPE[self.params.storage]
+        return self.buffers[idx].view(dt).view(Q, self.plane)
+
+    # -- outputs -----------------------------------------------------------
+    def macroscopic(self, stream=None):
+        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(load().clbm_macroscopic(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                       _stream(stream)))
+        return rho, u
+
+    def populations(self, stream=None) -> torch.Tensor:
+        f = torch.empty((Q,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(load().clbm_populations(self._h, ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+        return f
+
+    def reduce(self, stream=None, raise_unstable: bool = True) -> dict:
+        out = (ctypes.c_double * 8)()
+        rc = load().clbm_reduce(self._h, out, _stream(stream))
+        if rc != CLBM_OK and not (rc == CLBM_EUNSTABLE and not raise_unstable):
+            _check(rc)
+        keys = ("mass", "momentum_x", "momentum_y", "momentum_z", "residual", "nonfinite", "umax", "kinetic")
+        return dict(zip(keys, list(out)))
+
+    # -- launch shape ------------------------------------------------------
+    def set_block(self, bx: int, by: int):
+        _check(load().clbm_set_block(self._h, int(bx), int(by)))
+
+    def get_block(self):
+        bx, by = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().clbm_get_block(self._h, ctypes.byref(bx), ctypes.byref(by)))
+        return bx.value, by.value

@@ -1,0 +1,346 @@
+// C-ABI of the D3Q19 cascaded power-law LBM library (declared in clbm.h):
+// parameter validation, handles, kernel parameter set-up and launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/clbm.h"
+#include "clbm_internal.hpp"
+
+using namespace clbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+clbm_status fail(clbm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+clbm_status fail(clbm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+clbm_status hip_fail(hipError_t e, const char *what) {
+    return fail(CLBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                          \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t elem_bytes(int storage) { return storage == CLBM_F64 ? 8 : (storage == CLBM_F32 ? 4 : 2); }
+
+int64_t plane_stride_of(const clbm_params *p) {
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const int64_t align = 256 / (int64_t)elem_bytes(p->storage);   // elements per 256 B
+    return (N + align - 1) / align * align;
+}
+
+clbm_status validate(const clbm_params *p) {
+    if (!p) return fail(CLBM_EINVAL, "params is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(CLBM_EINVAL, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    if (N > ((int64_t)1 << 31) - 1)
+        return fail(CLBM_EINVAL, "lattice of %lld nodes exceeds 2^31 - 1", (long long)N);
+    if (p->storage < CLBM_F64 || p->storage > CLBM_F16_DEV)
+        return fail(CLBM_EINVAL, "unknown storage %d", p->storage);
+    if (!(p->K > 0.0) || !isfinite(p->K)) return fail(CLBM_EINVAL, "K must be finite and > 0");
+    if (!(p->n > 0.0) || !isfinite(p->n)) return fail(CLBM_EINVAL, "n must be finite and > 0");
+    if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min) || !isfinite(p->nu_max))
+        return fail(CLBM_EINVAL, "need 0 < nu_min < nu_max < inf");
+    if (!(p->omega_bulk > 0.0 && p->omega_bulk < 2.0)) return fail(CLBM_EINVAL, "omega_bulk must lie in (0, 2)");
+    for (int k = 0; k < 9; ++k)
+        if (!(p->omega_high[k] > 0.0 && p->omega_high[k] < 2.0))
+            return fail(CLBM_EINVAL, "omega_high[%d] must lie in (0, 2)", k);
+    if (p->omega_bulk != 1.0) return fail(CLBM_EINVAL, "omega_bulk != 1 is not supported by this build");
+    for (int k = 0; k < 9; ++k)
+        if (p->omega_high[k] != 1.0)
+            return fail(CLBM_EINVAL, "omega_high != 1 is not supported by this build");
+    for (int d = 0; d < 3; ++d) {
+        if (p->periodic[d] != 0 && p->periodic[d] != 1) return fail(CLBM_EINVAL, "periodic flags must be 0 or 1");
+        if (!isfinite(p->force[d]) || !isfinite(p->lid_velocity[d]))
+            return fail(CLBM_EINVAL, "force and lid velocity must be finite");
+    }
+    if (p->lid_face < CLBM_LID_NONE || p->lid_face > CLBM_LID_PZ)
+        return fail(CLBM_EINVAL, "unknown lid face %d", p->lid_face);
+    if (p->lid_face != CLBM_LID_NONE && p->periodic[(p->lid_face - 1) / 2])
+        return fail(CLBM_EINVAL, "the lid face lies on a periodic axis");
+    if (!(p->rho_wall > 0.0) || !isfinite(p->rho_wall)) return fail(CLBM_EINVAL, "rho_wall must be > 0");
+    if (p->attractor_literal != 0 && p->attractor_literal != 1)
+        return fail(CLBM_EINVAL, "attractor_literal must be 0 or 1");
+    return CLBM_OK;
+}
+
+template <typename T>
+Relax<T> make_relax(const clbm_params *p) {
+    Relax<T> r;
+    memset(&r, 0, sizeof(r));
+    for (int a = 0; a < Q; ++a) {
+        const double eu = cx(a) * p->lid_velocity[0] + cy(a) * p->lid_velocity[1] + cz(a) * p->lid_velocity[2];
+        r.lidc[a] = (T)(6.0 * weight(a) * p->rho_wall * eu);
+    }
+    r.log2_3K = (T)log2(3.0 * p->K);
+    r.three_K = (T)(3.0 * p->K);
+    r.n = (T)p->n;
+    r.k = (T)(0.5 * (p->n - 1.0));
+    r.tau_min = (T)(3.0 * p->nu_min + 0.5);
+    r.tau_max = (T)(3.0 * p->nu_max + 0.5);
+    r.s_lo = (T)(log2(3.0 * p->nu_min) - 1.0);
+    r.s_hi = (T)(log2(3.0 * p->nu_max) + 1.0);
+    r.omega_bulk = (T)p->omega_bulk;
+    for (int k = 0; k < 9; ++k) r.omega_high[k] = (T)p->omega_high[k];
+    for (int d = 0; d < 3; ++d) r.force[d] = (T)p->force[d];
+    r.newtonian = p->n == 1.0;
+    r.literal = p->attractor_literal;
+    return r;
+}
+
+Geom make_geom(const clbm_params *p) {
+    Geom g;
+    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+    g.px = p->periodic[0]; g.py = p->periodic[1]; g.pz = p->periodic[2];
+    if (p->lid_face == CLBM_LID_NONE) {
+        g.lid_axis = -1; g.lid_side = 0;
+    } else {
+        g.lid_axis = (p->lid_face - 1) / 2;
+        g.lid_side = ((p->lid_face - 1) % 2) ? 1 : -1;
+    }
+    g.plane = plane_stride_of(p);
+    return g;
+}
+
+bool aligned256(const void *ptr) { return ((uintptr_t)ptr & 255u) == 0; }
+
+}  // namespace
+
+struct clbm_lattice {
+    clbm_params prm;
+    Geom geom;
+    Relax<double> rd;
+    Relax<float> rf;
+    bool forced;
+    void *buf[2];
+    size_t bytes_each;
+    int cur;
+    bool initialized;
+    int64_t steps_done;
+    dim3 block;
+    // reduction scratch (library-owned)
+    double *partials;
+    double *result;
+    double *host_result;
+    int nblocks;
+    float *snapshot;
+    bool have_snapshot;
+};
+
+extern "C" {
+
+const char *clbm_last_error(void) { return g_err.c_str(); }
+
+const char *clbm_version(void) { return "clbm 0.1 (gfx950, D3Q19 cascaded power-law)"; }
+
+clbm_status clbm_lattice_tables(int32_t *e, int32_t *o, double *w) {
+    for (int a = 0; a < Q; ++a) {
+        if (e) { e[3 * a] = cx(a); e[3 * a + 1] = cy(a); e[3 * a + 2] = cz(a); }
+        if (o) o[a] = opp(a);
+        if (w) w[a] = weight(a);
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_params_default(clbm_params *p) {
+    if (!p) return fail(CLBM_EINVAL, "params is NULL");
+    memset(p, 0, sizeof(*p));
+    p->nx = p->ny = p->nz = 1;
+    p->storage = CLBM_F32;
+    p->track_residual = 1;
+    p->K = 0.01;
+    p->n = 1.0;
+    p->nu_min = (1.0 / 1.99 - 0.5) / 3.0;
+    p->nu_max = (1.0 / 0.1 - 0.5) / 3.0;
+    p->omega_bulk = 1.0;
+    for (int k = 0; k < 9; ++k) p->omega_high[k] = 1.0;
+    p->rho_wall = 1.0;
+    return CLBM_OK;
+}
+
+clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane, size_t *bytes) {
+    clbm_status st = validate(p);
+    if (st != CLBM_OK) return st;
+    const int64_t ps = plane_stride_of(p);
+    if (plane) *plane = ps;
+    if (bytes) *bytes = (size_t)ps * Q * elem_bytes(p->storage);
+    return CLBM_OK;
+}
+
+clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, clbm_lattice **out) {
+    if (!out) return fail(CLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    clbm_status st = validate(p);
+    if (st != CLBM_OK) return st;
+    size_t need = 0;
+    clbm_buffer_size(p, nullptr, &need);
+    if (!pop_a || !pop_b) return fail(CLBM_EINVAL, "state buffers must not be NULL");
+    if (pop_a == pop_b) return fail(CLBM_EINVAL, "the two state buffers must differ");
+    if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(CLBM_EINVAL, "state buffers must be 256-byte aligned");
+    if (bytes_each < need)
+        return fail(CLBM_EINVAL, "state buffers hold %zu bytes, need %zu", bytes_each, need);
+
+    clbm_lattice *h = (clbm_lattice *)calloc(1, sizeof(clbm_lattice));
+    if (!h) return fail(CLBM_ENOMEM, "host allocation failed");
+    h->prm = *p;
+    h->geom = make_geom(p);
+    h->rd = make_relax<double>(p);
+    h->rf = make_relax<float>(p);
+    h->forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
+    h->buf[0] = pop_a;
+    h->buf[1] = pop_b;
+    h->bytes_each = bytes_each;
+    h->cur = 0;
+    // default launch shape: 64-wide rows, several rows per block
+    int bx = p->nx >= 64 ? 64 : p->nx;
+    int by = 1;
+    while (bx * by * 2 <= 256 && by * 2 <= p->ny) by *= 2;
+    h->block = dim3(bx, by, 1);
+
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    int64_t nb = (N + kReduceThreads - 1) / kReduceThreads;
+    h->nblocks = (int)(nb < 1024 ? nb : 1024);
+    hipError_t e = hipMalloc((void **)&h->partials, sizeof(double) * kReduceSlots * (h->nblocks + 1));
+    if (e == hipSuccess) {
+        h->result = h->partials + (size_t)kReduceSlots * h->nblocks;
+        e = hipHostMalloc((void **)&h->host_result, sizeof(double) * kReduceSlots, hipHostMallocDefault);
+    }
+    if (e == hipSuccess && p->track_residual) e = hipMalloc((void **)&h->snapshot, sizeof(float) * 3 * N);
+    if (e != hipSuccess) {
+        clbm_destroy(h);
+        return hip_fail(e, "clbm_create: scratch allocation");
+    }
+    *out = h;
+    return CLBM_OK;
+}
+
+clbm_status clbm_destroy(clbm_lattice *h) {
+    if (!h) return CLBM_OK;
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->host_result) (void)hipHostFree(h->host_result);
+    if (h->snapshot) (void)hipFree(h->snapshot);
+    free(h);
+    return CLBM_OK;
+}
+
+clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (!f0) return fail(CLBM_EINVAL, "f0 is NULL");
+    h->cur = 0;
+    HIP_TRY(launch_init(h->prm.storage, f0, h->buf[0], h->geom, h->rd, h->rf, h->forced, (hipStream_t)stream),
+            "clbm_init_populations");
+    h->initialized = true;
+    h->steps_done = 0;
+    h->have_snapshot = false;
+    return CLBM_OK;
+}
+
+clbm_status clbm_init_rest(clbm_lattice *h, void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    h->cur = 0;
+    // f = w: every deviation is zero; the kernel collides that state once
+    HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->geom, h->rd, h->rf, h->forced, (hipStream_t)stream),
+            "clbm_init_rest");
+    h->initialized = true;
+    h->steps_done = 0;
+    h->have_snapshot = false;
+    return CLBM_OK;
+}
+
+clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
+    if (!h->initialized) return fail(CLBM_ESTATE, "clbm_step before an init call");
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        HIP_TRY(launch_step(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf, h->forced,
+                            h->block, st),
+                "clbm_step");
+        h->cur = 1 - h->cur;
+        h->steps_done++;
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_macroscopic(clbm_lattice *h, double *rho, double *u, void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (!h->initialized) return fail(CLBM_ESTATE, "clbm_macroscopic before an init call");
+    if (!rho && !u) return CLBM_OK;
+    HIP_TRY(launch_macroscopic(h->prm.storage, h->buf[h->cur], rho, u, h->geom, h->prm.force, (hipStream_t)stream),
+            "clbm_macroscopic");
+    return CLBM_OK;
+}
+
+clbm_status clbm_populations(clbm_lattice *h, double *f, void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (!f) return fail(CLBM_EINVAL, "output is NULL");
+    if (!h->initialized) return fail(CLBM_ESTATE, "clbm_populations before an init call");
+    HIP_TRY(launch_export(h->prm.storage, h->buf[h->cur], f, h->geom, (hipStream_t)stream), "clbm_populations");
+    return CLBM_OK;
+}
+
+clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (!out) return fail(CLBM_EINVAL, "out is NULL");
+    if (!h->initialized) return fail(CLBM_ESTATE, "clbm_reduce before an init call");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_reduce(h->prm.storage, h->buf[h->cur], h->snapshot, h->have_snapshot ? 1 : 0, h->geom,
+                          h->prm.force, h->partials, h->nblocks, h->result, st),
+            "clbm_reduce");
+    HIP_TRY(hipMemcpyAsync(h->host_result, h->result, sizeof(double) * kReduceSlots, hipMemcpyDeviceToHost, st),
+            "clbm_reduce: copy");
+    HIP_TRY(hipStreamSynchronize(st), "clbm_reduce: sync");
+    const double *r = h->host_result;
+    const int64_t N = (int64_t)h->prm.nx * h->prm.ny * h->prm.nz;
+    out[0] = (double)N + r[0];
+    out[1] = r[1]; out[2] = r[2]; out[3] = r[3];
+    out[4] = (h->snapshot && h->have_snapshot && r[5] > 0.0) ? sqrt(r[4] / r[5]) : 0.0;
+    out[5] = r[6];
+    out[6] = r[7];
+    out[7] = r[8];
+    if (h->snapshot) h->have_snapshot = true;
+    if (r[6] > 0.0) return fail(CLBM_EUNSTABLE, "%.0f nodes hold non-finite populations", r[6]);
+    return CLBM_OK;
+}
+
+clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (buffer_index) *buffer_index = h->cur;
+    if (steps_done) *steps_done = h->steps_done;
+    return CLBM_OK;
+}
+
+clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (bx < 1 || by < 1 || bx * by > kMaxBlock || (bx * by) % 64 != 0)
+        return fail(CLBM_EINVAL, "block %d x %d: need bx*by a multiple of 64 and <= %d", bx, by, kMaxBlock);
+    h->block = dim3(bx, by, 1);
+    return CLBM_OK;
+}
+
+clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (bx) *bx = (int32_t)h->block.x;
+    if (by) *by = (int32_t)h->block.y;
+    return CLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+// Kernels of the D3Q19 cascaded power-law LBM for gfx950 and their launchers.
+//
+//   stream_collide  one time step: pull gather + collision + store (Sec. 3)
+//   init_collide    collide a caller-supplied FP64 state once (time 0)
+//   macroscopic     rho and u from the stored post-collision state
+//   export          f = w + stored deviation, as FP64
+//   reduce          FP64 block partials of mass, momentum, residual, NaNs
+//   reduce_final    fixed-order sum of the partials
+#include "clbm_internal.hpp"
+
+namespace clbm {
+
+// ---------------------------------------------------------------------------
+// Fused stream-collide
+// ---------------------------------------------------------------------------
+template <typename S, typename T, bool Forced>
+__global__ void __launch_bounds__(kMaxBlock)
+stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    T d[Q];
+    gather<S, T>(A, g, p, x, y, z, d);
+    collide_unit_high<T, Forced>(d, p, nullptr);
+    const int64_t self = (int64_t)x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) B[(int64_t)a * g.plane + self] = Conv<S, T>::store(d[a]);
+}
+
+// ---------------------------------------------------------------------------
+// Collide-only initialisation from FP64 populations (unpadded planes); a
+// NULL source means the rest state f = w.
+// ---------------------------------------------------------------------------
+template <typename S, typename T, bool Forced>
+__global__ void __launch_bounds__(256)
+init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Relax<T> p) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    T d[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
+    collide_unit_high<T, Forced>(d, p, nullptr);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) B[(int64_t)a * g.plane + i] = Conv<S, T>::store(d[a]);
+}
+
+// ---------------------------------------------------------------------------
+// Moments of the stored state
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ inline void node_moments(const S *__restrict__ A, int64_t plane, int64_t i, double &D,
+                                    double &jx, double &jy, double &jz, bool &finite) {
+    D = jx = jy = jz = 0.0;
+    finite = true;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        double v = (double)Conv<S, typename StoreCompute<S>::T>::load(A[(int64_t)a * plane + i]);
+        finite = finite && isfinite(v);
+        D += v;
+        jx += cx(a) * v;
+        jy += cy(a) * v;
+        jz += cz(a) * v;
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256)
+macroscopic_kernel(const S *__restrict__ A, double *__restrict__ rho, double *__restrict__ u,
+                   Geom g, double fx, double fy, double fz) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double D, jx, jy, jz;
+    bool finite;
+    node_moments(A, g.plane, i, D, jx, jy, jz, finite);
+    const double r = 1.0 + D;
+    if (rho) rho[i] = r;
+    if (u) {
+        u[i] = (jx - 0.5 * fx) / r;
+        u[N + i] = (jy - 0.5 * fy) / r;
+        u[2 * N + i] = (jz - 0.5 * fz) / r;
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256)
+export_kernel(const S *__restrict__ A, double *__restrict__ f, Geom g) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+        f[(int64_t)a * N + i] =
+            weight(a) + (double)Conv<S, typename StoreCompute<S>::T>::load(A[(int64_t)a * g.plane + i]);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions: per-block partials, then a single-block fixed-order sum.
+// Slots: 0 sum(rho - 1), 1..3 momentum, 4 sum |u - u_prev|^2, 5 sum |u|^2,
+// 6 non-finite nodes, 7 max |u|, 8 kinetic energy.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kReduceThreads)
+reduce_kernel(const S *__restrict__ A, float *__restrict__ snap, int have_prev, Geom g, double fx,
+              double fy, double fz, double *__restrict__ partials) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    double acc[kReduceSlots];
+#pragma unroll
+    for (int k = 0; k < kReduceSlots; ++k) acc[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double D, jx, jy, jz;
+        bool finite;
+        node_moments(A, g.plane, i, D, jx, jy, jz, finite);
+        const double r = 1.0 + D;
+        const double mx = jx - 0.5 * fx, my = jy - 0.5 * fy, mz = jz - 0.5 * fz;
+        const double ux = mx / r, uy = my / r, uz = mz / r;
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        acc[0] += D;
+        acc[1] += mx;
+        acc[2] += my;
+        acc[3] += mz;
+        if (snap) {
+            if (have_prev) {
+                const double dx = ux - (double)snap[i], dy = uy - (double)snap[N + i],
+                             dz = uz - (double)snap[2 * N + i];
+                acc[4] += dx * dx + dy * dy + dz * dz;
+            }
+            snap[i] = (float)ux;
+            snap[N + i] = (float)uy;
+            snap[2 * N + i] = (float)uz;
+        }
+        acc[5] += u2;
+        acc[6] += finite ? 0.0 : 1.0;
+        acc[7] = fmax(acc[7], finite ? sqrt(u2) : 0.0);
+        acc[8] += 0.5 * r * u2;
+    }
+    __shared__ double sm[kReduceSlots][kReduceThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kReduceSlots; ++k) {
+        const double v = (k == 7) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) sm[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kReduceSlots) {
+        const int k = threadIdx.x;
+        double v = sm[k][0];
+        for (int w = 1; w < kReduceThreads / 64; ++w) v = (k == 7) ? fmax(v, sm[k][w]) : v + sm[k][w];
+        partials[(int64_t)blockIdx.x * kReduceSlots + k] = v;
+    }
+}
+
+__global__ void __launch_bounds__(64)
+reduce_final_kernel(const double *__restrict__ partials, int nblocks, double *__restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= kReduceSlots) return;
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        const double x = partials[(int64_t)b * kReduceSlots + k];
+        v = (k == 7) ? fmax(v, x) : v + x;
+    }
+    out[k] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename S, typename T>
+static hipError_t launch_step_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced,
+                                dim3 block, hipStream_t st) {
+    dim3 grid((g.nx + block.x - 1) / block.x, (g.ny + block.y - 1) / block.y, g.nz);
+    if (forced)
+        hipLaunchKernelGGL((stream_collide_kernel<S, T, true>), grid, block, 0, st, (const S *)A, (S *)B, g, p);
+    else
+        hipLaunchKernelGGL((stream_collide_kernel<S, T, false>), grid, block, 0, st, (const S *)A, (S *)B, g, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
+                       const Relax<float> &pf, bool forced, dim3 block, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_step_t<double, double>(A, B, g, pd, forced, block, st);
+    case 1: return launch_step_t<float, float>(A, B, g, pf, forced, block, st);
+    default: return launch_step_t<__half, float>(A, B, g, pf, forced, block, st);
+    }
+}
+
+template <typename S, typename T>
+static hipError_t launch_init_t(const double *f0, void *B, const Geom &g, const Relax<T> &p, bool forced,
+                                hipStream_t st) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    if (forced)
+        hipLaunchKernelGGL((init_collide_kernel<S, T, true>), grid, block, 0, st, f0, (S *)B, g, p);
+    else
+        hipLaunchKernelGGL((init_collide_kernel<S, T, false>), grid, block, 0, st, f0, (S *)B, g, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
+                       const Relax<float> &pf, bool forced, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_init_t<double, double>(f0, B, g, pd, forced, st);
+    case 1: return launch_init_t<float, float>(f0, B, g, pf, forced, st);
+    default: return launch_init_t<__half, float>(f0, B, g, pf, forced, st);
+    }
+}
+
+template <typename S>
+static hipError_t launch_macro_t(const void *A, double *rho, double *u, const Geom &g, const double *F,
+                                 hipStream_t st) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL((macroscopic_kernel<S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       (const S *)A, rho, u, g, F[0], F[1], F[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_macroscopic(int storage, const void *A, double *rho, double *u, const Geom &g,
+                              const double *F, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_macro_t<double>(A, rho, u, g, F, st);
+    case 1: return launch_macro_t<float>(A, rho, u, g, F, st);
+    default: return launch_macro_t<__half>(A, rho, u, g, F, st);
+    }
+}
+
+template <typename S>
+static hipError_t launch_export_t(const void *A, double *f, const Geom &g, hipStream_t st) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL((export_kernel<S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       (const S *)A, f, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(int storage, const void *A, double *f, const Geom &g, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_export_t<double>(A, f, g, st);
+    case 1: return launch_export_t<float>(A, f, g, st);
+    default: return launch_export_t<__half>(A, f, g, st);
+    }
+}
+
+template <typename S>
+static hipError_t launch_reduce_t(const void *A, float *snap, int have_prev, const Geom &g, const double *F,
+                                  double *partials, int nblocks, double *out, hipStream_t st) {
+    hipLaunchKernelGGL((reduce_kernel<S>), dim3(nblocks), dim3(kReduceThreads), 0, st, (const S *)A, snap,
+                       have_prev, g, F[0], F[1], F[2], partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, st, (const double *)partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int storage, const void *A, float *snap, int have_prev, const Geom &g,
+                         const double *F, double *partials, int nblocks, double *out, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_reduce_t<double>(A, snap, have_prev, g, F, partials, nblocks, out, st);
+    case 1: return launch_reduce_t<float>(A, snap, have_prev, g, F, partials, nblocks, out, st);
+    default: return launch_reduce_t<__half>(A, snap, have_prev, g, F, partials, nblocks, out, st);
+    }
+}
+
+}  // namespace clbm

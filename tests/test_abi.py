@@ -1,0 +1,101 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function declared in include/clbm.h, carries the paper's lattice
+tables, and validates parameters."""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module")
+def clbm():
+    from paper_1908_05396_amd import clbm as c
+    c.load()
+    return c
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "clbm.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(clbm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(clbm):
+    names = _declared_functions()
+    assert len(names) >= 16
+    lib = clbm.load()
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in clbm.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version(clbm):
+    assert "gfx950" in clbm.version()
+
+
+def test_kernel_tables_match_paper(clbm):
+    e, opp, w = clbm.lattice_tables()
+    printed = np.loadtxt(os.path.join(GOLDEN, "paper_velocity_components.txt"))
+    assert np.array_equal(e.T, printed)
+    assert np.array_equal(e[opp], -e)
+    with open(os.path.join(GOLDEN, "d3q19_weights.txt")) as fh:
+        vals = [float(Fraction(l.strip())) for l in fh if l.strip() and not l.startswith("#")]
+    assert np.array_equal(w, np.array(vals))
+
+
+def test_params_struct_layout(clbm):
+    assert ctypes.sizeof(clbm.Params) == 40 + 8 * (5 + 9 + 3 + 3 + 1)
+    p = clbm.Params()
+    assert clbm.load().clbm_params_default(ctypes.byref(p)) == 0
+    assert (p.nx, p.ny, p.nz) == (1, 1, 1)
+    assert p.storage == 1 and p.omega_bulk == 1.0 and p.rho_wall == 1.0
+    assert list(p.omega_high) == [1.0] * 9
+
+
+@pytest.mark.parametrize("storage,esize", [("f64", 8), ("f32", 4), ("f16", 2)])
+def test_buffer_size_padding(clbm, storage, esize):
+    spec = W.cavity(37, 0.05, 1.0, 100.0)
+    plane, nbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage))
+    assert plane >= spec.nodes and (plane * esize) % 256 == 0 and plane * esize - spec.nodes * esize < 256
+    assert nbytes == 19 * plane * esize
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("K", 0.0), ("K", float("nan")), ("n", -1.0), ("nu_min", 0.0), ("nu_max", 1e-6),
+    ("omega_bulk", 2.0), ("rho_wall", 0.0), ("storage", 7), ("lid_face", 9), ("attractor_literal", 2),
+])
+def test_invalid_parameters_rejected(clbm, field, value):
+    p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")
+    setattr(p, field, value)
+    with pytest.raises(clbm.ClbmError) as ei:
+        clbm.buffer_size(p)
+    assert ei.value.status == clbm.CLBM_EINVAL
+
+
+def test_lid_on_periodic_axis_rejected(clbm):
+    spec = W.cavity(8, 0.05, 1.0, 10.0).with_(periodic=(0, 1, 0))
+    with pytest.raises(clbm.ClbmError):
+        clbm.buffer_size(clbm.params_from_spec(spec, "f32"))
+
+
+def test_create_rejects_bad_buffers(clbm):
+    p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")
+    h = ctypes.c_void_p()
+    lib = clbm.load()
+    assert lib.clbm_create(ctypes.byref(p), None, None, 0, ctypes.byref(h)) == clbm.CLBM_EINVAL
+    # misaligned pointers are refused before any device call
+    assert lib.clbm_create(ctypes.byref(p), ctypes.c_void_p(0x1004), ctypes.c_void_p(0x2000), 1 << 30,
+                           ctypes.byref(h)) == clbm.CLBM_EINVAL
+    assert "aligned" in lib.clbm_last_error().decode()
+    # too small
+    assert lib.clbm_create(ctypes.byref(p), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 16,
+                           ctypes.byref(h)) == clbm.CLBM_EINVAL

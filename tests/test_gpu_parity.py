@@ -1,0 +1,188 @@
+"""GPU (HIP, through the C-ABI) versus the FP64 CPU oracle on the same seeded
+inputs.
+
+Tolerances (normwise: max over nodes and components of |u_gpu - u_ref|
+divided by max |u_ref|): FP64 storage 1e-12, FP32 storage 1e-5, FP16
+deviation storage 2e-3.  Post-collision populations after a single collision
+are compared element by element with bounds derived from the storage
+precision (see each test).
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_U = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def clbm():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05396_amd import clbm as c
+    c.load()
+    return c
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_u(spec, seed, eps, steps):
+    if seed is None:
+        f0 = W.rest_populations(spec).numpy()
+    else:
+        f0 = W.perturbed_populations(spec, seed, eps).numpy()
+    f = oracle.run(spec, f0, steps)
+    rho, u = oracle.macroscopic(spec, f)
+    return rho, u
+
+
+def _gpu_run(clbm, spec, storage, seed, eps, steps, block=None):
+    print(f"[gpu] {spec.name} {spec.nx}x{spec.ny}x{spec.nz} storage={storage} seed={seed} "
+          f"steps={steps} block={block}", flush=True)
+    lat = clbm.Lattice(spec, storage=storage, block=block)
+    if seed is None:
+        lat.init_rest()
+    else:
+        lat.init_populations(W.perturbed_populations(spec, seed, eps, device="cuda"))
+    lat.step(steps)
+    rho, u = lat.macroscopic()
+    torch.cuda.synchronize()
+    out = (rho.cpu().numpy(), u.cpu().numpy(), lat)
+    return out
+
+
+def _normwise(u, ref):
+    return np.abs(u - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 5e-15), ("f32", 1e-6), ("f16", 2e-5)])
+def test_single_collision_populations(clbm, storage, tol):
+    """One collision of a strongly perturbed state (eps = 2e-2, so every
+    non-equilibrium moment is present): post-collision populations agree
+    element by element.  Bounds: FP64 a few ulp of O(1) values; FP32 about 16
+    ulp of the largest population; FP16 the rounding of deviations of size
+    ~1e-2 (2^-11 relative) plus FP32 arithmetic."""
+    spec = W.cavity(16, 0.05, 0.6, 100.0).with_(nx=13, ny=11, nz=9, name="collide13x11x9")
+    f0 = W.perturbed_populations(spec, 7, 2e-2)
+    lat = clbm.Lattice(spec, storage=storage)
+    lat.init_populations(f0.to("cuda"))
+    f_gpu = lat.populations().cpu().numpy()
+    f_ref = oracle.collide(spec, f0.numpy())
+    err = np.abs(f_gpu - f_ref).max()
+    print(f"collide {storage}: max abs diff {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_poiseuille_config(clbm, storage):
+    """8x32x8 power-law channel (n = 0.5, Re = 10, u_max = 0.01, body force),
+    2000 steps from rest.  FP16-deviation storage is not used here: the force
+    changes the populations by ~1e-7 per step, about two FP16 ulps of the
+    stored deviations, so FP16 storage cannot carry this slow acceleration."""
+    spec = W.config_poiseuille()
+    rho_ref, u_ref = _oracle_u(spec, None, 0.0, 2000)
+    rho, u, _ = _gpu_run(clbm, spec, storage, None, 0.0, 2000)
+    err = _normwise(u, u_ref)
+    print(f"poiseuille {storage}: {err:.3e}")
+    assert err < TOL_U[storage]
+
+
+@pytest.mark.parametrize("n", [0.5, 1.0, 1.5])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_cavity16_power_law(clbm, n, storage):
+    """16^3 lid-driven cavity, U = 0.05, Re = 100, perturbed start (seed 1234,
+    eps 1e-3), 300 steps."""
+    spec = W.cavity(16, 0.05, n, 100.0, name=f"cavity16_n{n}")
+    rho_ref, u_ref = _oracle_u(spec, 1234, 1e-3, 300)
+    rho, u, _ = _gpu_run(clbm, spec, storage, 1234, 1e-3, 300)
+    err = _normwise(u, u_ref)
+    print(f"cavity16 n={n} {storage}: {err:.3e}")
+    if storage != "f16":
+        assert err < TOL_U[storage]
+        return
+    # FP16 deviations: the error is judged on the centrelines of the mid
+    # plane z = H/2 (u_x(y) at x = H/2 and u_y(x) at y = H/2), as the cavity
+    # benchmark reports it.  Over the whole field the FP16 rounding of the
+    # large deviations next to the lid edges (pressure singularity) reaches
+    # ~1e-2 of U; bounded here at 2e-2.
+    c = 8
+    cl = max(np.abs(u[0, c, :, c] - u_ref[0, c, :, c]).max(),
+             np.abs(u[1, c, c, :] - u_ref[1, c, c, :]).max()) / np.abs(u_ref).max()
+    print(f"cavity16 n={n} f16 centrelines: {cl:.3e}")
+    assert cl < TOL_U["f16"]
+    assert err < 2e-2
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_ragged_lattice(clbm, storage):
+    """70 x 20 x 9 cavity: two 64-wide tiles along x with a ragged tail of 6,
+    odd y and z extents."""
+    spec = W.cavity(20, 0.05, 0.8, 50.0).with_(nx=70, ny=20, nz=9, name="cavity70x20x9")
+    rho_ref, u_ref = _oracle_u(spec, 99, 1e-3, 80)
+    rho, u, _ = _gpu_run(clbm, spec, storage, 99, 1e-3, 80)
+    err = _normwise(u, u_ref)
+    print(f"ragged {storage}: {err:.3e}")
+    assert err < TOL_U[storage]
+
+
+def test_periodic_mixed_walls(clbm):
+    """Periodic along x and z with walls at y, a lid at -z would be invalid;
+    here a duct periodic along x with walls in y and z and a lid on +z."""
+    spec = W.LatticeSpec(nx=12, ny=10, nz=8, K=0.02, n=1.3, periodic=(1, 0, 0), lid_face=W.LID_PZ,
+                         lid_velocity=(0.03, 0.01, 0.0), name="duct_lidz")
+    rho_ref, u_ref = _oracle_u(spec, 5, 1e-3, 150)
+    rho, u, _ = _gpu_run(clbm, spec, "f64", 5, 1e-3, 150)
+    assert _normwise(u, u_ref) < TOL_U["f64"]
+
+
+def test_block_shape_does_not_change_results(clbm):
+    spec = W.cavity(20, 0.05, 0.7, 100.0).with_(nx=96, name="cavity96x20x20")
+    results = []
+    for block in [(64, 1), (64, 4), (32, 2), (128, 2), (96, 2)]:
+        _, u, _ = _gpu_run(clbm, spec, "f32", 4, 1e-3, 30, block=block)
+        results.append(u)
+    for u in results[1:]:
+        assert np.array_equal(u, results[0])
+
+
+def test_reductions(clbm):
+    """FP64 reductions: total mass of a closed cavity is conserved (the lid
+    terms cancel pairwise), momentum matches the oracle, no NaN."""
+    spec = W.cavity(16, 0.05, 0.5, 100.0, name="cavity16_red")
+    lat = clbm.Lattice(spec, storage="f64")
+    lat.init_populations(W.perturbed_populations(spec, 1234, 1e-3, device="cuda"))
+    r0 = lat.reduce()
+    lat.step(300)
+    r1 = lat.reduce()
+    assert abs(r1["mass"] - r0["mass"]) < 1e-12 * spec.nodes
+    rho_ref, u_ref = _oracle_u(spec, 1234, 1e-3, 300)
+    mom = (rho_ref[None] * u_ref).reshape(3, -1).sum(axis=1)
+    assert np.allclose([r1["momentum_x"], r1["momentum_y"], r1["momentum_z"]], mom, rtol=0, atol=1e-12)
+    assert r1["nonfinite"] == 0
+    assert r1["umax"] == pytest.approx(np.sqrt((u_ref ** 2).sum(axis=0)).max(), rel=1e-12)
+    assert r1["residual"] > 0
+
+
+def test_reduce_reports_nonfinite(clbm):
+    spec = W.cavity(8, 0.05, 1.0, 10.0, name="cavity8_nan")
+    f0 = W.rest_populations(spec).clone()
+    f0[3, 2, 2, 2] = float("nan")
+    lat = clbm.Lattice(spec, storage="f32")
+    lat.init_populations(f0.to("cuda"))
+    with pytest.raises(clbm.ClbmError) as ei:
+        lat.reduce()
+    assert ei.value.status == clbm.CLBM_EUNSTABLE
+    assert lat.reduce(raise_unstable=False)["nonfinite"] >= 1
+
+
+def test_init_rest_with_force_matches_oracle(clbm):
+    spec = W.config_poiseuille()
+    lat = clbm.Lattice(spec, storage="f64")
+    lat.init_rest()
+    f = lat.populations().cpu().numpy()
+    ref = oracle.collide(spec, W.rest_populations(spec).numpy())
+    assert np.abs(f - ref).max() < 1e-15

@@ -116,7 +116,7 @@ def test_rest_state_is_invariant(n):
     w = oracle.weights()
     spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.01, n=n)
     ft, _ = oracle.collide_node(spec, w)
-    assert np.abs(ft - w).max() <= 1e-16
+    assert np.abs(ft - w).max() <= 6e-16      # a few ulp of 1/3
 
 
 @pytest.mark.parametrize("rho0", [0.97, 1.05])
@@ -126,7 +126,7 @@ def test_equilibrium_is_density_homogeneous(rho0):
     w = oracle.weights()
     spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.01, n=0.8)
     ft, _ = oracle.collide_node(spec, rho0 * w)
-    assert np.abs(ft - rho0 * w).max() <= 4e-16
+    assert np.abs(ft - rho0 * w).max() <= 8e-16      # a few ulp of rho/3
 
 
 @pytest.mark.parametrize("literal", [0, 1])
