@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the D3Q19 cascaded power-law stream-collide step.
+
+Workload (default): lid-driven cubic cavity 512^3 (134.2 M nodes), Re = 3200,
+n = 0.75, lid velocity 0.04, rest start; FP32 storage of f - w with FP32
+arithmetic; the FP64 mass reduction every 100 steps tracks the mass drift.
+One step = one fused pull stream-collide launch over the whole lattice.
+
+Prints ONE JSON line: MLUPS of the timed region (exactly --steps steps after
+--warmup untimed ones, bracketed by device synchronisation), the roofline of
+the stream-collide kernel (algorithmic bytes per launch / average launch time
+measured with events on the launch stream), the FP16-deviation and FP64
+storage variants of the same workload, the achievable copy bandwidth, and the
+CPU oracle timed on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+BYTES_PER_LUP = {"f64": 304, "f32": 152, "f16": 76}   # 19 reads + 19 writes per node update
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_05396_amd", "csrc", f)
+                  for f in ("clbm_device.hpp", "clbm_kernels.hip")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload, or None if absent or taken on other sources."""
+    path = os.path.join(PROFILE_DIR, f"stream_collide_{workload}_{storage}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None):
+    """Run warmup + timed steps; returns timing and reduction results."""
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block)
+    lat.init_rest()
+    r0 = lat.reduce()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts, ends = [], []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        chunk = min(reduce_every, steps - done)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(chunk)
+        e1.record(stream)
+        starts.append((e0, chunk))
+        ends.append(e1)
+        done += chunk
+        if done < steps or done % reduce_every == 0:
+            lat.reduce()          # FP64 mass/NaN check every `reduce_every` steps (synchronizes)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = sum(e0.elapsed_time(e1) for (e0, _), e1 in zip(starts, ends))
+    r1 = lat.reduce()
+    out = {
+        "wall_s": wall,
+        "ms_per_step": wall * 1e3 / steps,
+        "kernel_ms_per_launch": kernel_ms / steps,
+        "mass_drift": (r1["mass"] - r0["mass"]) / r0["mass"],
+        "umax": r1["umax"],
+        "nonfinite": r1["nonfinite"],
+        "block": list(lat.get_block()),
+    }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline(storage, nodes, kernel_ms, workload):
+    achieved = BYTES_PER_LUP[storage] * nodes / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(storage, workload),
+            "bytes_per_lup": BYTES_PER_LUP[storage]}
+
+
+def copy_bandwidth(clbm, torch, nbytes=4 << 30, reps=10):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    clbm.copy_probe(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        clbm.copy_probe(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(spec_full, min_seconds=10.0, max_seconds=30.0):
+    """The FP64 oracle on the host cores, on a 64^3 cavity with the same
+    power-law parameters (K, n, lid velocity) as the full workload, stepped
+    until at least `min_seconds` have elapsed."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    threads = oracle.set_threads(len(os.sched_getaffinity(0)))
+    sub = spec_full.with_(nx=64, ny=64, nz=64, name="cpu_sample")
+    f = W.rest_populations(sub).numpy()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = oracle.run(sub, f, 2)
+        steps += 2
+        el = time.perf_counter() - t0
+        if el >= min_seconds or el >= max_seconds:
+            break
+    mlups = sub.nodes * steps / el / 1e6
+    assert np.isfinite(f).all()
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, 64^3 cavity with the workload's K, n and lid velocity, "
+                      f"{steps} steps from rest, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--size", type=int, default=512, help="cavity edge length")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--reduce-every", type=int, default=100)
+    ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's "
+                                   "multi-GPU decomposition is not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_1908_05396_amd import clbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spec = W.config_cavity512() if args.size == 512 else \
+        W.cavity(args.size, 0.04, 0.75, 3200.0, name=f"cavity{args.size}_re3200_n0.75")
+    workload = spec.name
+
+    main_run = time_lattice(clbm, torch, spec, args.storage, args.steps, args.warmup, args.reduce_every)
+    mlups = spec.nodes * args.steps / (main_run["ms_per_step"] * args.steps * 1e-3) / 1e6
+
+    variants = {}
+    if not args.no_variants:
+        for st in ("f16", "f64", "f32"):
+            if st == args.storage:
+                continue
+            r = time_lattice(clbm, torch, spec, st, args.variant_steps, 20, args.reduce_every)
+            variants[st] = {
+                "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+                "roofline": roofline(st, spec.nodes, r["kernel_ms_per_launch"], workload),
+                "kernel_ms_per_launch": round(r["kernel_ms_per_launch"], 4),
+                "mass_drift": r["mass_drift"], "steps": args.variant_steps,
+            }
+
+    line = {
+        "metric": "MLUPS & %HBM roofline, D3Q19 cascaded power-law; FP32/FP16-store vs FP64",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "nodes": spec.nodes, "storage": args.storage,
+                   "lid_velocity": spec.lid_velocity[0], "Re": 3200.0, "n": spec.n, "K": spec.K,
+                   "init": "rest", "reduce_every": args.reduce_every, "block": main_run["block"]},
+        "roofline": roofline(args.storage, spec.nodes, main_run["kernel_ms_per_launch"], workload),
+        "kernel_ms_per_launch": round(main_run["kernel_ms_per_launch"], 4),
+        "mass_drift": main_run["mass_drift"],
+        "variants": variants,
+    }
+    if not args.no_copy:
+        line["copy_gbs"] = round(copy_bandwidth(clbm, torch), 1)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

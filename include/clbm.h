@@ -82,6 +82,9 @@ typedef struct {
     int32_t attractor_literal; /* 0: fourth-order attractors kxx*kyy/rho (default);
                                   1: kxx*kyy as printed (linearly unstable, for study only) */
     int32_t track_residual;    /* 1: keep a velocity snapshot for the steady-state residual */
+    int32_t plane_pad;         /* extra elements between population planes (>= 0), on top of the
+                                  256-byte rounding; -1: library default (see clbm_buffer_size) */
+    int32_t reserved;          /* must be 0 */
     double K;                  /* consistency coefficient mu_p > 0 (Eq. 5) */
     double n;                  /* power-law index n > 0 (Eq. 5; n = 1 Newtonian) */
     double nu_min, nu_max;     /* clip of the apparent kinematic viscosity mu/rho,
@@ -100,9 +103,11 @@ typedef struct clbm_lattice clbm_lattice;
  * omega in [0.1, 1.99], omega_bulk = omega_high = 1, no force, rho_wall = 1. */
 clbm_status clbm_params_default(clbm_params *p);
 
-/* Elements per population plane for these dimensions and storage (padded so
- * every plane starts 256-byte aligned), and the bytes one state buffer needs
- * (19 planes).  Either output pointer may be NULL. */
+/* Elements per population plane for these dimensions and storage: nx*ny*nz
+ * rounded up to 256 bytes, plus plane_pad elements (default: 256 bytes more
+ * when the rounded plane is a multiple of 64 KiB, so the 19 planes do not all
+ * start on the same HBM channel), and the bytes one state buffer needs (19
+ * planes).  Either output pointer may be NULL. */
 clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane_stride, size_t *bytes);
 
 /* Create a lattice over two caller-owned state buffers of `bytes_each` bytes
@@ -148,9 +153,22 @@ clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream);
  * the number of steps taken since the last init. */
 clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done);
 
-/* Launch shape of the stream-collide kernel: threads per block along x and y
- * (bx*by in {64,...,1024}, bx a multiple of 64 or equal to nx).  Used by the
- * autotuner; the default is chosen at create. */
+/* Launch configuration of the stream-collide kernel (results do not depend
+ * on it; only speed does). */
+typedef struct {
+    int32_t bx, by;      /* threads per block along x and y: bx*by a multiple of 64, at most
+                            512 (FP32/FP16 storage) or 256 (FP64) */
+    int32_t xcd_remap;   /* 1: workgroup b takes tile (b mod 8)*(B/8) + b/8, so each of the
+                            eight XCDs sweeps a contiguous slab of the lattice */
+    int32_t nt_loads;    /* 1: non-temporal hint on population loads */
+    int32_t nt_stores;   /* 1: non-temporal hint on population stores */
+    int32_t reserved;    /* must be 0 */
+} clbm_launch;
+
+clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *cfg);
+clbm_status clbm_get_launch(clbm_lattice *h, clbm_launch *cfg);
+
+/* Shorthands for the block shape alone. */
 clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by);
 clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by);
 
@@ -158,6 +176,13 @@ clbm_status clbm_destroy(clbm_lattice *h);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *clbm_last_error(void);
+
+/* Measurement utility: copy `bytes` (a multiple of 16) from src to dst
+ * (device memory, 16-byte aligned, not overlapping) with a plain streaming
+ * kernel.  Gives the achievable HBM bandwidth of the device and the
+ * calibration of hardware byte counters against a kernel of known traffic.
+ * Asynchronous on `stream`. */
+clbm_status clbm_copy_probe(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Version string and the lattice tables compiled into the kernels (for
  * tests): e[3*alpha + c], opposite[alpha], w[alpha]. */

@@ -35,6 +35,8 @@ class Params(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("attractor_literal", ctypes.c_int32),
         ("track_residual", ctypes.c_int32),
+        ("plane_pad", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("K", ctypes.c_double), ("n", ctypes.c_double),
         ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
         ("omega_bulk", ctypes.c_double),
@@ -43,6 +45,11 @@ class Params(ctypes.Structure):
         ("lid_velocity", ctypes.c_double * 3),
         ("rho_wall", ctypes.c_double),
     ]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("nt_loads", ctypes.c_int32), ("nt_stores", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -62,12 +69,15 @@ SIGNATURES = {
     "clbm_populations": (ctypes.c_int, [_VP, _VP, _VP]),
     "clbm_reduce": (ctypes.c_int, [_VP, _DP, _VP]),
     "clbm_state": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int), _I64P]),
+    "clbm_set_launch": (ctypes.c_int, [_VP, ctypes.POINTER(Launch)]),
+    "clbm_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(Launch)]),
     "clbm_set_block": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "clbm_get_block": (ctypes.c_int, [_VP, _I32P, _I32P]),
     "clbm_destroy": (ctypes.c_int, [_VP]),
     "clbm_last_error": (ctypes.c_char_p, []),
     "clbm_version": (ctypes.c_char_p, []),
     "clbm_lattice_tables": (ctypes.c_int, [_I32P, _I32P, _DP]),
+    "clbm_copy_probe": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
 }
 
 
@@ -107,7 +117,16 @@ def lattice_tables():
     return (np.array(list(e), dtype=np.int64).reshape(Q, 3), np.array(list(o)), np.array(list(w)))
 
 
-def params_from_spec(spec, storage: str = "f32", track_residual: bool = True) -> Params:
+def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Plain device copy of src into dst (bandwidth reference)."""
+    nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
+    nbytes -= nbytes % 16
+    _check(load().clbm_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  ctypes.c_size_t(nbytes), _stream(stream)))
+    return nbytes
+
+
+def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, plane_pad: int = -1) -> Params:
     """Fill the C parameter struct from a problem description with the
     attributes of workloads.LatticeSpec."""
     p = Params()
@@ -121,6 +140,7 @@ def params_from_spec(spec, storage: str = "f32", track_residual: bool = True) ->
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.attractor_literal = int(getattr(spec, "attractor_literal", 0))
     p.track_residual = 1 if track_residual else 0
+    p.plane_pad = int(plane_pad)
     p.K, p.n = float(spec.K), float(spec.n)
     p.nu_min, p.nu_max = float(spec.nu_min), float(spec.nu_max)
     p.omega_bulk = float(spec.omega_bulk)
@@ -148,11 +168,11 @@ class Lattice:
     handle, and thin wrappers of the C calls."""
 
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
-                 block=None):
+                 block=None, plane_pad: int = -1, launch: dict = None):
         lib = load()
         self.spec = spec
         self.storage = storage
-        self.params = params_from_spec(spec, storage, track_residual)
+        self.params = params_from_spec(spec, storage, track_residual, plane_pad)
         self.plane, self.nbytes = buffer_size(self.params)
         self.device = torch.device(device)
         self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
@@ -163,6 +183,8 @@ class Lattice:
         self._h = h
         if block is not None:
             self.set_block(*block)
+        if launch:
+            self.set_launch(**launch)
 
     @property
     def nodes(self) -> int:
@@ -235,6 +257,18 @@ class Lattice:
     # -- launch shape ------------------------------------------------------
     def set_block(self, bx: int, by: int):
         _check(load().clbm_set_block(self._h, int(bx), int(by)))
+
+    def set_launch(self, **kw):
+        c = Launch()
+        _check(load().clbm_get_launch(self._h, ctypes.byref(c)))
+        for k, v in kw.items():
+            setattr(c, k, int(v))
+        _check(load().clbm_set_launch(self._h, ctypes.byref(c)))
+
+    def get_launch(self) -> dict:
+        c = Launch()
+        _check(load().clbm_get_launch(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in Launch._fields_ if k != "reserved"}
 
     def get_block(self):
         bx, by = ctypes.c_int32(), ctypes.c_int32()

@@ -43,7 +43,13 @@ size_t elem_bytes(int storage) { return storage == CLBM_F64 ? 8 : (storage == CL
 int64_t plane_stride_of(const clbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t align = 256 / (int64_t)elem_bytes(p->storage);   // elements per 256 B
-    return (N + align - 1) / align * align;
+    int64_t plane = (N + align - 1) / align * align;
+    if (p->plane_pad >= 0) {
+        plane += (p->plane_pad + align - 1) / align * align;
+    } else if ((plane * (int64_t)elem_bytes(p->storage)) % 65536 == 0) {
+        plane += align;
+    }
+    return plane;
 }
 
 clbm_status validate(const clbm_params *p) {
@@ -51,10 +57,12 @@ clbm_status validate(const clbm_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(CLBM_EINVAL, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-    if (N > ((int64_t)1 << 31) - 1)
-        return fail(CLBM_EINVAL, "lattice of %lld nodes exceeds 2^31 - 1", (long long)N);
     if (p->storage < CLBM_F64 || p->storage > CLBM_F16_DEV)
         return fail(CLBM_EINVAL, "unknown storage %d", p->storage);
+    // one population plane is addressed through a buffer descriptor with a
+    // 32-bit byte range
+    if (N * (int64_t)elem_bytes(p->storage) > ((int64_t)1 << 32) - 256)
+        return fail(CLBM_EINVAL, "lattice of %lld nodes: one population plane exceeds 4 GiB", (long long)N);
     if (!(p->K > 0.0) || !isfinite(p->K)) return fail(CLBM_EINVAL, "K must be finite and > 0");
     if (!(p->n > 0.0) || !isfinite(p->n)) return fail(CLBM_EINVAL, "n must be finite and > 0");
     if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min) || !isfinite(p->nu_max))
@@ -79,6 +87,8 @@ clbm_status validate(const clbm_params *p) {
     if (!(p->rho_wall > 0.0) || !isfinite(p->rho_wall)) return fail(CLBM_EINVAL, "rho_wall must be > 0");
     if (p->attractor_literal != 0 && p->attractor_literal != 1)
         return fail(CLBM_EINVAL, "attractor_literal must be 0 or 1");
+    if (p->plane_pad < -1 || p->plane_pad > (1 << 24)) return fail(CLBM_EINVAL, "plane_pad out of range");
+    if (p->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
     return CLBM_OK;
 }
 
@@ -109,6 +119,8 @@ Relax<T> make_relax(const clbm_params *p) {
 Geom make_geom(const clbm_params *p) {
     Geom g;
     g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+    g.nxy = p->nx * p->ny;
+    g.n = p->nx * p->ny * p->nz;
     g.px = p->periodic[0]; g.py = p->periodic[1]; g.pz = p->periodic[2];
     if (p->lid_face == CLBM_LID_NONE) {
         g.lid_axis = -1; g.lid_side = 0;
@@ -135,7 +147,7 @@ struct clbm_lattice {
     int cur;
     bool initialized;
     int64_t steps_done;
-    dim3 block;
+    StepLaunch launch;
     // reduction scratch (library-owned)
     double *partials;
     double *result;
@@ -160,12 +172,21 @@ clbm_status clbm_lattice_tables(int32_t *e, int32_t *o, double *w) {
     return CLBM_OK;
 }
 
+clbm_status clbm_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst) return fail(CLBM_EINVAL, "copy probe: NULL pointer");
+    if (bytes % 16 != 0 || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
+        return fail(CLBM_EINVAL, "copy probe: bytes and pointers must be multiples of 16");
+    HIP_TRY(launch_copy_probe(src, dst, bytes, (hipStream_t)stream), "clbm_copy_probe");
+    return CLBM_OK;
+}
+
 clbm_status clbm_params_default(clbm_params *p) {
     if (!p) return fail(CLBM_EINVAL, "params is NULL");
     memset(p, 0, sizeof(*p));
     p->nx = p->ny = p->nz = 1;
     p->storage = CLBM_F32;
     p->track_residual = 1;
+    p->plane_pad = -1;
     p->K = 0.01;
     p->n = 1.0;
     p->nu_min = (1.0 / 1.99 - 0.5) / 3.0;
@@ -210,10 +231,17 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
     h->bytes_each = bytes_each;
     h->cur = 0;
     // default launch shape: 64-wide rows, several rows per block
-    int bx = p->nx >= 64 ? 64 : p->nx;
+    // default launch: up to 256 threads along x (whole 64-wide waves), rows
+    // stacked along y when the lattice is narrow
+    int bx = p->nx >= 256 ? 256 : (p->nx >= 64 ? 64 * (p->nx / 64) : p->nx);
+    if (bx > 256) bx = 256;
     int by = 1;
     while (bx * by * 2 <= 256 && by * 2 <= p->ny) by *= 2;
-    h->block = dim3(bx, by, 1);
+    h->launch.bx = bx;
+    h->launch.by = by;
+    h->launch.xcd_remap = 0;
+    h->launch.nt_loads = 0;
+    h->launch.nt_stores = 1;    // streaming stores: the new state is not re-read this step
 
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     int64_t nb = (N + kReduceThreads - 1) / kReduceThreads;
@@ -272,7 +300,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     for (int64_t t = 0; t < nsteps; ++t) {
         HIP_TRY(launch_step(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf, h->forced,
-                            h->block, st),
+                            h->launch, st),
                 "clbm_step");
         h->cur = 1 - h->cur;
         h->steps_done++;
@@ -328,18 +356,45 @@ clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done) 
     return CLBM_OK;
 }
 
+clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
+    if (!h || !c) return fail(CLBM_EINVAL, "NULL argument");
+    const int maxt = h->prm.storage == CLBM_F64 ? 256 : 512;
+    if (c->bx < 1 || c->by < 1 || c->bx * c->by > maxt || (c->bx * c->by) % 64 != 0)
+        return fail(CLBM_EINVAL, "block %d x %d: need bx*by a multiple of 64 and <= %d", c->bx, c->by, maxt);
+    if ((c->xcd_remap | c->nt_loads | c->nt_stores) & ~1) return fail(CLBM_EINVAL, "launch flags must be 0 or 1");
+    if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
+    h->launch.bx = c->bx;
+    h->launch.by = c->by;
+    h->launch.xcd_remap = c->xcd_remap;
+    h->launch.nt_loads = c->nt_loads;
+    h->launch.nt_stores = c->nt_stores;
+    return CLBM_OK;
+}
+
+clbm_status clbm_get_launch(clbm_lattice *h, clbm_launch *c) {
+    if (!h || !c) return fail(CLBM_EINVAL, "NULL argument");
+    c->bx = h->launch.bx;
+    c->by = h->launch.by;
+    c->xcd_remap = h->launch.xcd_remap;
+    c->nt_loads = h->launch.nt_loads;
+    c->nt_stores = h->launch.nt_stores;
+    c->reserved = 0;
+    return CLBM_OK;
+}
+
 clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
-    if (bx < 1 || by < 1 || bx * by > kMaxBlock || (bx * by) % 64 != 0)
-        return fail(CLBM_EINVAL, "block %d x %d: need bx*by a multiple of 64 and <= %d", bx, by, kMaxBlock);
-    h->block = dim3(bx, by, 1);
-    return CLBM_OK;
+    clbm_launch c;
+    clbm_get_launch(h, &c);
+    c.bx = bx;
+    c.by = by;
+    return clbm_set_launch(h, &c);
 }
 
 clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
-    if (bx) *bx = (int32_t)h->block.x;
-    if (by) *by = (int32_t)h->block.y;
+    if (bx) *bx = h->launch.bx;
+    if (by) *by = h->launch.by;
     return CLBM_OK;
 }
 

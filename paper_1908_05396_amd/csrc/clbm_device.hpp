@@ -58,10 +58,61 @@ template <> struct Conv<__half, float> {
 // ---------------------------------------------------------------------------
 struct Geom {
     int32_t nx, ny, nz;
+    int32_t nxy;            // nx * ny
+    int32_t n;              // nx * ny * nz (< 2^31)
     int32_t px, py, pz;     // periodic flags
     int32_t lid_axis;       // 0, 1, 2, or -1 for no lid
     int32_t lid_side;       // +1: the ghost plane beyond n-1; -1: the one before 0
     int64_t plane;          // elements per population plane
+};
+
+// ---------------------------------------------------------------------------
+// Plane access through raw buffer descriptors: one descriptor per population
+// plane (base = plane start, range = n elements), 32-bit byte offsets from a
+// VGPR.  Offsets outside the range return 0 without touching memory, so the
+// interior pull can run unguarded and edge lanes are patched afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kBufferFlags = 0x00020000;   // raw (untyped) buffer, gfx9 family
+
+template <typename S, int Aux = 0> struct Plane;
+template <int Aux> struct Plane<float, Aux> {
+    __device__ static float load(const float *A, const Geom &g, int a, uint32_t i) {
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * 4u), kBufferFlags);
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4u), 0, Aux));
+    }
+    __device__ static void store(float *B, const Geom &g, int a, uint32_t i, float v) {
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * 4u), kBufferFlags);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)(i * 4u), 0, Aux);
+    }
+};
+template <int Aux> struct Plane<double, Aux> {
+    __device__ static double load(const double *A, const Geom &g, int a, uint32_t i) {
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * 8u), kBufferFlags);
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 8u), 0, Aux));
+    }
+    __device__ static void store(double *B, const Geom &g, int a, uint32_t i, double v) {
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * 8u), kBufferFlags);
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(i * 8u), 0, Aux);
+    }
+};
+template <int Aux> struct Plane<__half, Aux> {
+    __device__ static float load(const __half *A, const Geom &g, int a, uint32_t i) {
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * 2u), kBufferFlags);
+        return __half2float(
+            __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)(i * 2u), 0, Aux)));
+    }
+    __device__ static void store(__half *B, const Geom &g, int a, uint32_t i, float v) {
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * 2u), kBufferFlags);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, __float2half_rn(v)), r,
+                                              (int)(i * 2u), 0, Aux);
+    }
 };
 
 template <typename T> struct Relax {
@@ -96,19 +147,29 @@ template <typename T> struct Relax {
 // linear in s, so Newton from the tau = 1 estimate converges in a few steps.
 // The clipped solution is the unclipped root clamped to [tau_min, tau_max].
 template <typename T> struct NewtonTol;
+// FP32: four iterations from the tau = 1 estimate reach full precision over
+// n in [0.4, 1.6], K over five decades and a over twelve (checked against a
+// bisection reference); FP64 iterates to convergence.
 template <> struct NewtonTol<float> {
-    static constexpr int maxit = 8;
-    static constexpr float tol = 3e-4f;     // one more step after this is exact to FP32
+    static constexpr bool fixed = true;
+    static constexpr int maxit = 4;
+    static constexpr float tol = 0.0f;
 };
 template <> struct NewtonTol<double> {
+    static constexpr bool fixed = false;
     static constexpr int maxit = 16;
     static constexpr double tol = 1e-9;     // one more step after this is exact to FP64
 };
 
-__device__ inline float fast_log2(float x) { return __log2f(x); }
-__device__ inline float fast_exp2(float x) { return exp2f(x); }
+// FP32: the hardware log2/exp2/reciprocal (about 1 ulp); the arguments stay
+// in the normal range (tau - 1/2 in [2^-10, 2^5], q handled by the window).
+// FP64: library log2/exp2, reciprocal refined to full precision.
+__device__ inline float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double fast_log2(double x) { return log2(x); }
 __device__ inline double fast_exp2(double x) { return exp2(x); }
+__device__ inline double fast_rcp(double x) { return 1.0 / x; }
 
 template <typename T>
 __device__ inline T clampv(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
@@ -118,7 +179,7 @@ __device__ inline T clampv(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
 // and the final clamp of tau gives the clipped viscosity, as required.
 template <typename T>
 __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
-    if (p.newtonian) return clampv(T(0.5) + p.three_K / rho, p.tau_min, p.tau_max);
+    if (p.newtonian) return clampv(T(0.5) + p.three_K * fast_rcp(rho), p.tau_min, p.tau_max);
     const T q0 = a + b;
     if (q0 == T(0)) {
         // no shear: the power law gives nu -> infinity (n < 1) or 0 (n > 1)
@@ -126,15 +187,20 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
     }
     const T c = p.log2_3K - p.n * fast_log2(rho);
     T s = clampv(c + p.k * fast_log2(q0), p.s_lo, p.s_hi);   // exact if tau were 1
+    const T two_k = T(2) * p.k;
     bool last = false;
     for (int it = 0; it < NewtonTol<T>::maxit; ++it) {
         const T e = fast_exp2(s);                 // tau - 1/2
-        const T it1 = T(1) / (T(0.5) + e);        // 1/tau
-        const T it2 = it1 * it1;
-        const T q = a * it2 + b;
+        const T it1 = fast_rcp(T(0.5) + e);       // 1/tau
+        const T q = a * (it1 * it1) + b;
         const T phi = s - c - p.k * fast_log2(q);
-        const T dphi = T(1) + T(2) * p.k * a * e * it2 * it1 / q;
-        const T sn = clampv(s - phi / dphi, p.s_lo, p.s_hi);
+        // slope 1 + 2k (a / (tau^2 q)) (tau - 1/2) / tau, with a/(tau^2 q) = 1 - b/q
+        const T dphi = T(1) + two_k * (T(1) - b * fast_rcp(q)) * (e * it1);
+        const T sn = clampv(s - phi * fast_rcp(dphi), p.s_lo, p.s_hi);
+        if (NewtonTol<T>::fixed) {
+            s = sn;
+            continue;
+        }
         const T ds = sn - s;
         s = sn;
         if (last) break;
@@ -169,7 +235,7 @@ __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out
     T Mxx = Fx + Exy + Exz, Myy = Fy + Exy + Eyz, Mzz = Fz + Exz + Eyz;   // minus 1/3
 
     const T rho = T(1) + D;
-    const T irho = T(1) / rho;
+    const T irho = fast_rcp(rho);
     T fx = T(0), fy = T(0), fz = T(0);
     if (Forced) {
         fx = p.force[0]; fy = p.force[1]; fz = p.force[2];
@@ -192,7 +258,7 @@ __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out
     const T a = T(3) * (m7 * m7 - m7 * m8 + m8 * m8) + T(9) * (kxy * kxy + kxz * kxz + kyz * kyz);
     const T b = T(1.5) * m9 * m9;   // omega_9 = 1
     const T tau = solve_tau(p, rho, a, b);
-    const T om = T(1) / tau;
+    const T om = fast_rcp(tau);
     if (omega_out) *omega_out = om;
     const T r = T(1) - om;
 
@@ -303,45 +369,58 @@ __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out
 // bounce-back returns the population this node sent toward the wall,
 // d_opp(a)(x) (deviations: w_a = w_opp(a)), plus the moving-wall term when the
 // ghost belongs to the lid plane.
+// Pull along one direction with the full wall logic (used for lanes on the
+// lattice edge): periodic wrap, half-way bounce-back, moving lid.
 template <typename S, typename T>
-__device__ inline void gather(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y,
-                              int z, T d[Q]) {
-    const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t self = (int64_t)x + (int64_t)g.nx * y + nxy * z;
-    // source coordinate for each direction component c in {-1, 0, +1}: x - c
-    int sx[3], sy[3], sz[3];
-    bool wx[3], wy[3], wz[3];
-#pragma unroll
-    for (int c = -1; c <= 1; ++c) {
-        int vx = x - c, vy = y - c, vz = z - c;
-        bool ox = vx < 0 || vx >= g.nx, oy = vy < 0 || vy >= g.ny, oz = vz < 0 || vz >= g.nz;
-        if (g.px) vx = vx < 0 ? vx + g.nx : (vx >= g.nx ? vx - g.nx : vx);
-        if (g.py) vy = vy < 0 ? vy + g.ny : (vy >= g.ny ? vy - g.ny : vy);
-        if (g.pz) vz = vz < 0 ? vz + g.nz : (vz >= g.nz ? vz - g.nz : vz);
-        sx[c + 1] = vx; sy[c + 1] = vy; sz[c + 1] = vz;
-        wx[c + 1] = ox && !g.px; wy[c + 1] = oy && !g.py; wz[c + 1] = oz && !g.pz;
-    }
-    // lid: ghost in the lid plane along the lid axis
-    int lc = 0;
+__device__ inline T pull_edge(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int a, int x, int y,
+                              int z, uint32_t self) {
+    const int ex = cx(a), ey = cy(a), ez = cz(a);
+    int sx = x - ex, sy = y - ey, sz = z - ez;
+    bool wall = false;
+    if (sx < 0 || sx >= g.nx) { if (g.px) sx = sx < 0 ? sx + g.nx : sx - g.nx; else wall = true; }
+    if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
+    if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
+    if (!wall) return (T)Plane<S>::load(A, g, a, (uint32_t)(sx + g.nx * sy + g.nxy * sz));
+    T v = (T)Plane<S>::load(A, g, opp(a), self);
     if (g.lid_axis >= 0) {
-        const int coord = g.lid_axis == 0 ? x : (g.lid_axis == 1 ? y : z);
+        // the ghost lies in the lid plane when the source coordinate along the
+        // lid axis is just beyond the lid face
+        const int sc = g.lid_axis == 0 ? x - ex : (g.lid_axis == 1 ? y - ey : z - ez);
         const int nmax = g.lid_axis == 0 ? g.nx : (g.lid_axis == 1 ? g.ny : g.nz);
-        // source beyond the +side plane needs e = -1 along the axis at coord n-1
-        if (g.lid_side > 0 && coord == nmax - 1) lc = -1;
-        if (g.lid_side < 0 && coord == 0) lc = 1;
+        if ((g.lid_side > 0 && sc == nmax) || (g.lid_side < 0 && sc == -1)) v += p.lidc[a];
     }
+    return v;
+}
+
+// Pull gather (Eq. cascaded streaming with the wall rules of Sec. 4).  Node
+// (x, y, z) receives along e_a the post-collision population that left
+// (x, y, z) - e_a.  Interior lanes read at a uniform offset per direction;
+// lanes on the lattice edge redo the directions that cross it with the full
+// rule (half-way bounce-back returns d_opp(a)(x) since w_a = w_opp(a), plus
+// the moving-wall term in the lid plane; periodic axes wrap).
+template <typename S, typename T, int LdAux = 0>
+__device__ inline void gather(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
+                              uint32_t self, T d[Q]) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        const int ex = cx(a), ey = cy(a), ez = cz(a);
-        const bool wall = wx[ex + 1] || wy[ey + 1] || wz[ez + 1];
-        const int64_t src = (int64_t)sx[ex + 1] + (int64_t)g.nx * sy[ey + 1] + nxy * sz[ez + 1];
-        const int64_t idx = wall ? (int64_t)opp(a) * g.plane + self : (int64_t)a * g.plane + src;
-        T v = Conv<S, T>::load(A[idx]);
-        if (g.lid_axis >= 0 && lc != 0) {
-            const int ec = g.lid_axis == 0 ? ex : (g.lid_axis == 1 ? ey : ez);
-            if (wall && ec == lc) v += p.lidc[a];
+        const int off = -(cx(a) + cy(a) * g.nx + cz(a) * g.nxy);
+        d[a] = (T)Plane<S, LdAux>::load(A, g, a, self + (uint32_t)off);
+    }
+    const bool yz_edge = y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1;
+    if (yz_edge) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+    } else {
+        if (x == 0) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                if (cx(a) == 1) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
         }
-        d[a] = v;
+        if (x == g.nx - 1) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                if (cx(a) == -1) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+        }
     }
 }
 

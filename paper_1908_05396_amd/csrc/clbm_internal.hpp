@@ -11,15 +11,31 @@ template <> struct StoreCompute<float> { using T = float; };
 template <> struct StoreCompute<__half> { using T = float; };
 
 constexpr int kReduceThreads = 256;
-constexpr int kMaxBlock = 256;      // threads per stream-collide block
+// threads per stream-collide block: FP32 arithmetic needs < 128 VGPRs, FP64
+// about 160, which allows four waves per block
+template <typename T> struct MaxThreads { static constexpr int value = 512; };
+template <> struct MaxThreads<double> { static constexpr int value = 256; };
+
+struct LaunchGrid {
+    uint32_t gx, gy, gz;    // tiles along x, y and z layers
+    uint32_t aligned;       // largest multiple of 8 <= number of workgroups
+    int32_t remap;          // XCD-contiguous tile order
+};
+
+struct StepLaunch {
+    int32_t bx, by;         // threads per block along x and y
+    int32_t xcd_remap;
+    int32_t nt_loads, nt_stores;
+};
 constexpr int kReduceSlots = 9;
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, dim3 block, hipStream_t st);
+                       const Relax<float> &pf, bool forced, const StepLaunch &c, hipStream_t st);
 hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
                        const Relax<float> &pf, bool forced, hipStream_t st);
 hipError_t launch_macroscopic(int storage, const void *A, double *rho, double *u, const Geom &g,
                               const double *F, hipStream_t st);
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_export(int storage, const void *A, double *f, const Geom &g, hipStream_t st);
 hipError_t launch_reduce(int storage, const void *A, float *snap, int have_prev, const Geom &g,
                          const double *F, double *partials, int nblocks, double *out, hipStream_t st);

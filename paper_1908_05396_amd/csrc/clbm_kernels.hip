@@ -13,19 +13,29 @@ namespace clbm {
 // ---------------------------------------------------------------------------
 // Fused stream-collide
 // ---------------------------------------------------------------------------
-template <typename S, typename T, bool Forced>
-__global__ void __launch_bounds__(kMaxBlock)
-stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+// One thread per node, blocks of (blockDim.x, blockDim.y) nodes in the
+// x-y plane of one z layer, launched as a 1-D grid.  Consecutive workgroups
+// are dispatched round-robin to the eight XCDs; with `remap` set, workgroup b
+// takes the tile (b mod 8) * (B/8) + b / 8, so each XCD sweeps a contiguous
+// slab and the neighbour rows a node pulls from sit in the same L2.
+template <typename S, typename T, bool Forced, int LdAux, int StAux>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, LaunchGrid L) {
+    uint32_t b = blockIdx.x;
+    if (L.remap && b < L.aligned) b = (b & 7u) * (L.aligned >> 3) + (b >> 3);
+    const uint32_t tx = b % L.gx;
+    b /= L.gx;
+    const uint32_t ty = b % L.gy;
+    const int z = (int)(b / L.gy);
+    const int x = (int)(tx * blockDim.x + threadIdx.x);
+    const int y = (int)(ty * blockDim.y + threadIdx.y);
     if (x >= g.nx || y >= g.ny) return;
+    const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
     T d[Q];
-    gather<S, T>(A, g, p, x, y, z, d);
+    gather<S, T, LdAux>(A, g, p, x, y, z, self, d);
     collide_unit_high<T, Forced>(d, p, nullptr);
-    const int64_t self = (int64_t)x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) B[(int64_t)a * g.plane + self] = Conv<S, T>::store(d[a]);
+    for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B, g, a, self, d[a]);
 }
 
 // ---------------------------------------------------------------------------
@@ -43,7 +53,7 @@ init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Re
     for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
     collide_unit_high<T, Forced>(d, p, nullptr);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) B[(int64_t)a * g.plane + i] = Conv<S, T>::store(d[a]);
+    for (int a = 0; a < Q; ++a) Plane<S>::store(B, g, a, (uint32_t)i, d[a]);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,25 +185,60 @@ reduce_final_kernel(const double *__restrict__ partials, int nblocks, double *__
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Plain streaming copy (bandwidth reference)
 // ---------------------------------------------------------------------------
-template <typename S, typename T>
-static hipError_t launch_step_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced,
-                                dim3 block, hipStream_t st) {
-    dim3 grid((g.nx + block.x - 1) / block.x, (g.ny + block.y - 1) / block.y, g.nz);
-    if (forced)
-        hipLaunchKernelGGL((stream_collide_kernel<S, T, true>), grid, block, 0, st, (const S *)A, (S *)B, g, p);
-    else
-        hipLaunchKernelGGL((stream_collide_kernel<S, T, false>), grid, block, 0, st, (const S *)A, (S *)B, g, p);
+__global__ void __launch_bounds__(256)
+copy_probe_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st) {
+    const int64_t n = (int64_t)(bytes / 16);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (const float4 *)src,
+                       (float4 *)dst, n);
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename S, typename T, bool Forced>
+static hipError_t launch_step_f(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
+                                hipStream_t st) {
+    LaunchGrid L;
+    L.gx = (g.nx + c.bx - 1) / c.bx;
+    L.gy = (g.ny + c.by - 1) / c.by;
+    L.gz = g.nz;
+    const uint32_t nb = (uint32_t)L.gx * L.gy * L.gz;
+    L.aligned = nb & ~7u;
+    L.remap = c.xcd_remap;
+    dim3 grid(nb), block(c.bx, c.by);
+    const int mode = (c.nt_loads ? 1 : 0) | (c.nt_stores ? 2 : 0);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
+    case 1: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 0>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
+    case 2: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
+    default: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 2>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename S, typename T>
+static hipError_t launch_step_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced,
+                                const StepLaunch &c, hipStream_t st) {
+    return forced ? launch_step_f<S, T, true>(A, B, g, p, c, st) : launch_step_f<S, T, false>(A, B, g, p, c, st);
+}
+
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, dim3 block, hipStream_t st) {
+                       const Relax<float> &pf, bool forced, const StepLaunch &c, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_step_t<double, double>(A, B, g, pd, forced, block, st);
-    case 1: return launch_step_t<float, float>(A, B, g, pf, forced, block, st);
-    default: return launch_step_t<__half, float>(A, B, g, pf, forced, block, st);
+    case 0: return launch_step_t<double, double>(A, B, g, pd, forced, c, st);
+    case 1: return launch_step_t<float, float>(A, B, g, pf, forced, c, st);
+    default: return launch_step_t<__half, float>(A, B, g, pf, forced, c, st);
     }
 }
 

@@ -53,7 +53,7 @@ def test_kernel_tables_match_paper(clbm):
 
 
 def test_params_struct_layout(clbm):
-    assert ctypes.sizeof(clbm.Params) == 40 + 8 * (5 + 9 + 3 + 3 + 1)
+    assert ctypes.sizeof(clbm.Params) == 48 + 8 * (5 + 9 + 3 + 3 + 1)
     p = clbm.Params()
     assert clbm.load().clbm_params_default(ctypes.byref(p)) == 0
     assert (p.nx, p.ny, p.nz) == (1, 1, 1)
@@ -66,6 +66,12 @@ def test_buffer_size_padding(clbm, storage, esize):
     spec = W.cavity(37, 0.05, 1.0, 100.0)
     plane, nbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage))
     assert plane >= spec.nodes and (plane * esize) % 256 == 0 and plane * esize - spec.nodes * esize < 256
+    # a plane of 2^k bytes gets 256 bytes of padding by default (HBM channel spread)
+    pow2 = W.cavity(64, 0.05, 1.0, 100.0)
+    plane2, _ = clbm.buffer_size(clbm.params_from_spec(pow2, storage))
+    assert plane2 * esize == pow2.nodes * esize + 256
+    plane3, _ = clbm.buffer_size(clbm.params_from_spec(pow2, storage, plane_pad=0))
+    assert plane3 == pow2.nodes
     assert nbytes == 19 * plane * esize
 
 
