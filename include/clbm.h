@@ -66,6 +66,18 @@ typedef enum {
     CLBM_F16_DEV = 2  /* FP16 storage of f - w, FP32 arithmetic */
 } clbm_storage;
 
+/* Two algebraically equivalent forms of the collision (they agree to
+ * rounding; see tests): the central-moment form relaxes each central-moment
+ * combination and maps the raw-moment changes back to populations, and is
+ * specialised to omega_9 = omega_10..18 = 1 (the paper's choice); the printed
+ * form evaluates the changes of moments g4..g18 and f~ = f + K.g (Sec. 3.1,
+ * 3.3) for any omega_9, omega_10..18. */
+typedef enum {
+    CLBM_COLLIDE_AUTO = 0,     /* central-moment form when omega_9..18 are all 1, else printed form */
+    CLBM_COLLIDE_CENTRAL = 1,  /* requires omega_9..18 = 1 */
+    CLBM_COLLIDE_GHAT = 2
+} clbm_collision;
+
 typedef enum {
     CLBM_LID_NONE = 0, CLBM_LID_MX = 1, CLBM_LID_PX = 2, CLBM_LID_MY = 3,
     CLBM_LID_PY = 4, CLBM_LID_MZ = 5, CLBM_LID_PZ = 6
@@ -84,7 +96,7 @@ typedef struct {
     int32_t track_residual;    /* 1: keep a velocity snapshot for the steady-state residual */
     int32_t plane_pad;         /* extra elements between population planes (>= 0), on top of the
                                   256-byte rounding; -1: library default (see clbm_buffer_size) */
-    int32_t reserved;          /* must be 0 */
+    int32_t collision;         /* clbm_collision: which algebraic form of the collision runs */
     double K;                  /* consistency coefficient mu_p > 0 (Eq. 5) */
     double n;                  /* power-law index n > 0 (Eq. 5; n = 1 Newtonian) */
     double nu_min, nu_max;     /* clip of the apparent kinematic viscosity mu/rho,
@@ -99,8 +111,9 @@ typedef struct {
 typedef struct clbm_lattice clbm_lattice;
 
 /* Defaults: 1x1x1, no periodic axis, no lid, FP32 storage, normalized
- * attractors, residual tracking on, K = 0.01, n = 1, viscosity clip for
- * omega in [0.1, 1.99], omega_bulk = omega_high = 1, no force, rho_wall = 1. */
+ * attractors, residual tracking on, default plane padding, automatic
+ * collision form, K = 0.01, n = 1, viscosity clip for omega in [0.1, 1.99],
+ * omega_bulk = omega_high = 1, no force, rho_wall = 1. */
 clbm_status clbm_params_default(clbm_params *p);
 
 /* Elements per population plane for these dimensions and storage: nx*ny*nz

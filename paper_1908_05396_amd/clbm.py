@@ -16,6 +16,7 @@ LIBPATH = os.path.join(_HERE, "libclbm.so")
 
 Q = 19
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+COLLISION = {"auto": 0, "central": 1, "ghat": 2}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
 
 CLBM_OK, CLBM_EINVAL, CLBM_ENOMEM, CLBM_EHIP, CLBM_EUNSTABLE, CLBM_ESTATE = 0, -1, -2, -3, -4, -5
@@ -36,7 +37,7 @@ class Params(ctypes.Structure):
         ("attractor_literal", ctypes.c_int32),
         ("track_residual", ctypes.c_int32),
         ("plane_pad", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
         ("K", ctypes.c_double), ("n", ctypes.c_double),
         ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
         ("omega_bulk", ctypes.c_double),
@@ -126,7 +127,8 @@ def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
     return nbytes
 
 
-def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, plane_pad: int = -1) -> Params:
+def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, plane_pad: int = -1,
+                     collision: str = "auto") -> Params:
     """Fill the C parameter struct from a problem description with the
     attributes of workloads.LatticeSpec."""
     p = Params()
@@ -141,6 +143,7 @@ def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, pl
     p.attractor_literal = int(getattr(spec, "attractor_literal", 0))
     p.track_residual = 1 if track_residual else 0
     p.plane_pad = int(plane_pad)
+    p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     p.K, p.n = float(spec.K), float(spec.n)
     p.nu_min, p.nu_max = float(spec.nu_min), float(spec.nu_max)
     p.omega_bulk = float(spec.omega_bulk)
@@ -168,11 +171,11 @@ class Lattice:
     handle, and thin wrappers of the C calls."""
 
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
-                 block=None, plane_pad: int = -1, launch: dict = None):
+                 block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto"):
         lib = load()
         self.spec = spec
         self.storage = storage
-        self.params = params_from_spec(spec, storage, track_residual, plane_pad)
+        self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision)
         self.plane, self.nbytes = buffer_size(self.params)
         self.device = torch.device(device)
         self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]

@@ -52,6 +52,19 @@ int64_t plane_stride_of(const clbm_params *p) {
     return plane;
 }
 
+bool unit_high_omegas(const clbm_params *p) {
+    if (p->omega_bulk != 1.0) return false;
+    for (int k = 0; k < 9; ++k)
+        if (p->omega_high[k] != 1.0) return false;
+    return true;
+}
+
+int route_of(const clbm_params *p) {
+    if (p->collision == CLBM_COLLIDE_GHAT) return 1;
+    if (p->collision == CLBM_COLLIDE_CENTRAL) return 0;
+    return unit_high_omegas(p) ? 0 : 1;
+}
+
 clbm_status validate(const clbm_params *p) {
     if (!p) return fail(CLBM_EINVAL, "params is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
@@ -71,10 +84,10 @@ clbm_status validate(const clbm_params *p) {
     for (int k = 0; k < 9; ++k)
         if (!(p->omega_high[k] > 0.0 && p->omega_high[k] < 2.0))
             return fail(CLBM_EINVAL, "omega_high[%d] must lie in (0, 2)", k);
-    if (p->omega_bulk != 1.0) return fail(CLBM_EINVAL, "omega_bulk != 1 is not supported by this build");
-    for (int k = 0; k < 9; ++k)
-        if (p->omega_high[k] != 1.0)
-            return fail(CLBM_EINVAL, "omega_high != 1 is not supported by this build");
+    if (p->collision < CLBM_COLLIDE_AUTO || p->collision > CLBM_COLLIDE_GHAT)
+        return fail(CLBM_EINVAL, "unknown collision form %d", p->collision);
+    if (p->collision == CLBM_COLLIDE_CENTRAL && !unit_high_omegas(p))
+        return fail(CLBM_EINVAL, "the central-moment form needs omega_bulk = omega_high = 1");
     for (int d = 0; d < 3; ++d) {
         if (p->periodic[d] != 0 && p->periodic[d] != 1) return fail(CLBM_EINVAL, "periodic flags must be 0 or 1");
         if (!isfinite(p->force[d]) || !isfinite(p->lid_velocity[d]))
@@ -88,7 +101,6 @@ clbm_status validate(const clbm_params *p) {
     if (p->attractor_literal != 0 && p->attractor_literal != 1)
         return fail(CLBM_EINVAL, "attractor_literal must be 0 or 1");
     if (p->plane_pad < -1 || p->plane_pad > (1 << 24)) return fail(CLBM_EINVAL, "plane_pad out of range");
-    if (p->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
     return CLBM_OK;
 }
 
@@ -96,10 +108,7 @@ template <typename T>
 Relax<T> make_relax(const clbm_params *p) {
     Relax<T> r;
     memset(&r, 0, sizeof(r));
-    for (int a = 0; a < Q; ++a) {
-        const double eu = cx(a) * p->lid_velocity[0] + cy(a) * p->lid_velocity[1] + cz(a) * p->lid_velocity[2];
-        r.lidc[a] = (T)(6.0 * weight(a) * p->rho_wall * eu);
-    }
+    for (int d = 0; d < 3; ++d) r.lid6[d] = (T)(6.0 * p->rho_wall * p->lid_velocity[d]);
     r.log2_3K = (T)log2(3.0 * p->K);
     r.three_K = (T)(3.0 * p->K);
     r.n = (T)p->n;
@@ -123,10 +132,11 @@ Geom make_geom(const clbm_params *p) {
     g.n = p->nx * p->ny * p->nz;
     g.px = p->periodic[0]; g.py = p->periodic[1]; g.pz = p->periodic[2];
     if (p->lid_face == CLBM_LID_NONE) {
-        g.lid_axis = -1; g.lid_side = 0;
+        g.lid_axis = -1; g.lid_side = 0; g.lid_mask = 0;
     } else {
         g.lid_axis = (p->lid_face - 1) / 2;
         g.lid_side = ((p->lid_face - 1) % 2) ? 1 : -1;
+        g.lid_mask = 1 << (p->lid_face - 1);
     }
     g.plane = plane_stride_of(p);
     return g;
@@ -142,6 +152,7 @@ struct clbm_lattice {
     Relax<double> rd;
     Relax<float> rf;
     bool forced;
+    int route;
     void *buf[2];
     size_t bytes_each;
     int cur;
@@ -226,6 +237,7 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
     h->rd = make_relax<double>(p);
     h->rf = make_relax<float>(p);
     h->forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
+    h->route = route_of(p);
     h->buf[0] = pop_a;
     h->buf[1] = pop_b;
     h->bytes_each = bytes_each;
@@ -273,7 +285,8 @@ clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, void *strea
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     if (!f0) return fail(CLBM_EINVAL, "f0 is NULL");
     h->cur = 0;
-    HIP_TRY(launch_init(h->prm.storage, f0, h->buf[0], h->geom, h->rd, h->rf, h->forced, (hipStream_t)stream),
+    HIP_TRY(launch_init(h->prm.storage, f0, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
+                        (hipStream_t)stream),
             "clbm_init_populations");
     h->initialized = true;
     h->steps_done = 0;
@@ -285,7 +298,8 @@ clbm_status clbm_init_rest(clbm_lattice *h, void *stream) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     h->cur = 0;
     // f = w: every deviation is zero; the kernel collides that state once
-    HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->geom, h->rd, h->rf, h->forced, (hipStream_t)stream),
+    HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
+                        (hipStream_t)stream),
             "clbm_init_rest");
     h->initialized = true;
     h->steps_done = 0;
@@ -300,7 +314,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     for (int64_t t = 0; t < nsteps; ++t) {
         HIP_TRY(launch_step(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf, h->forced,
-                            h->launch, st),
+                            h->route, h->launch, st),
                 "clbm_step");
         h->cur = 1 - h->cur;
         h->steps_done++;

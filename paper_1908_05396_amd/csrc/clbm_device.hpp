@@ -63,6 +63,7 @@ struct Geom {
     int32_t px, py, pz;     // periodic flags
     int32_t lid_axis;       // 0, 1, 2, or -1 for no lid
     int32_t lid_side;       // +1: the ghost plane beyond n-1; -1: the one before 0
+    int32_t lid_mask;       // bit f-1 set for lid face f (1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z)
     int64_t plane;          // elements per population plane
 };
 
@@ -116,7 +117,7 @@ template <int Aux> struct Plane<__half, Aux> {
 };
 
 template <typename T> struct Relax {
-    T lidc[Q];              // moving-wall term 2 w_a rho_w (e_a . U_w) / c_s^2 per direction
+    T lid6[3];              // 6 rho_w U_w: the moving-wall term is w_a (e_a . lid6)
     T log2_3K;              // log2(3 K)
     T three_K;              // 3 K
     T n;                    // power-law index
@@ -207,6 +208,50 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
         if (fabs(ds) < NewtonTol<T>::tol) last = true;   // quadratic convergence: one more step
     }
     return clampv(T(0.5) + fast_exp2(s), p.tau_min, p.tau_max);
+}
+
+// ---------------------------------------------------------------------------
+// d += M0^{-1} dR: populations whose raw moments (monomials 1, x, y, z, xy,
+// xz, yz, xx, yy, zz, xyy, xzz, xxy, yzz, xxz, yyz, xxyy, xxzz, yyzz) are dR.
+// Each edge population is fixed by the four moments of its plane, each face
+// pair by its axis moments minus the edge contributions, and the rest
+// population by mass.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void add_raw_moment_change(T d[Q], T dR0, T dRx, T dRy, T dRz, T dRxy, T dRxz, T dRyz, T dRxx,
+                                             T dRyy, T dRzz, T dRxyy, T dRxzz, T dRxxy, T dRyzz, T dRxxz,
+                                             T dRyyz, T dRxxyy, T dRxxzz, T dRyyzz) {
+    const T q = T(0.25), h = T(0.5);
+    {
+        const T s0 = dRxxyy + dRxy, s1 = dRxyy + dRxxy, s2 = dRxxyy - dRxy, s3 = dRxyy - dRxxy;
+        d[7] += q * (s0 + s1);
+        d[10] += q * (s0 - s1);
+        d[8] += q * (s2 - s3);
+        d[9] += q * (s2 + s3);
+    }
+    {
+        const T s0 = dRxxzz + dRxz, s1 = dRxzz + dRxxz, s2 = dRxxzz - dRxz, s3 = dRxzz - dRxxz;
+        d[11] += q * (s0 + s1);
+        d[14] += q * (s0 - s1);
+        d[12] += q * (s2 - s3);
+        d[13] += q * (s2 + s3);
+    }
+    {
+        const T s0 = dRyyzz + dRyz, s1 = dRyzz + dRyyz, s2 = dRyyzz - dRyz, s3 = dRyzz - dRyyz;
+        d[15] += q * (s0 + s1);
+        d[18] += q * (s0 - s1);
+        d[16] += q * (s2 - s3);
+        d[17] += q * (s2 + s3);
+    }
+    {
+        const T ex = dRxx - dRxxyy - dRxxzz, ox = dRx - dRxyy - dRxzz;
+        const T ey = dRyy - dRxxyy - dRyyzz, oy = dRy - dRxxy - dRyzz;
+        const T ez = dRzz - dRxxzz - dRyyzz, oz = dRz - dRxxz - dRyyz;
+        d[1] += h * (ex + ox); d[2] += h * (ex - ox);
+        d[3] += h * (ey + oy); d[4] += h * (ey - oy);
+        d[5] += h * (ez + oz); d[6] += h * (ez - oz);
+    }
+    d[0] += dR0 + (dRxxyy + dRxxzz + dRyyzz) - (dRxx + dRyy + dRzz);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,48 +372,204 @@ __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out
     const T dRyyz = Ryyz - ((d[15] - d[18]) + (d[16] - d[17]));
     const T dRxxyy = Rxxyy - Exy, dRxxzz = Rxxzz - Exz, dRyyzz = Ryyzz - Eyz;
 
-    // Omega from the raw-moment changes (inverse of the monomial moment map)
-    const T q = T(0.25), h = T(0.5);
-    {
-        const T s0 = dRxxyy + dRxy, s1 = dRxyy + dRxxy, s2 = dRxxyy - dRxy, s3 = dRxyy - dRxxy;
-        d[7] += q * (s0 + s1);
-        d[10] += q * (s0 - s1);
-        d[8] += q * (s2 - s3);
-        d[9] += q * (s2 + s3);
-    }
-    {
-        const T s0 = dRxxzz + dRxz, s1 = dRxzz + dRxxz, s2 = dRxxzz - dRxz, s3 = dRxzz - dRxxz;
-        d[11] += q * (s0 + s1);
-        d[14] += q * (s0 - s1);
-        d[12] += q * (s2 - s3);
-        d[13] += q * (s2 + s3);
-    }
-    {
-        const T s0 = dRyyzz + dRyz, s1 = dRyzz + dRyyz, s2 = dRyyzz - dRyz, s3 = dRyzz - dRyyz;
-        d[15] += q * (s0 + s1);
-        d[18] += q * (s0 - s1);
-        d[16] += q * (s2 - s3);
-        d[17] += q * (s2 + s3);
-    }
-    {
-        const T ex = dRxx - dRxxyy - dRxxzz, ox = dRx - dRxyy - dRxzz;
-        const T ey = dRyy - dRxxyy - dRyyzz, oy = dRy - dRxxy - dRyzz;
-        const T ez = dRzz - dRxxzz - dRyyzz, oz = dRz - dRxxz - dRyyz;
-        d[1] += h * (ex + ox); d[2] += h * (ex - ox);
-        d[3] += h * (ey + oy); d[4] += h * (ey - oy);
-        d[5] += h * (ez + oz); d[6] += h * (ez - oz);
-    }
-    d[0] += (dRxxyy + dRxxzz + dRyyzz) - (dRxx + dRyy + dRzz);
+    add_raw_moment_change<T>(d, T(0), dRx, dRy, dRz, dRxy, dRxz, dRyz, dRxx, dRyy, dRzz, dRxyy, dRxzz, dRxxy,
+                             dRyzz, dRxxz, dRyyz, dRxxyy, dRxxzz, dRyyzz);
 }
 
 // ---------------------------------------------------------------------------
-// Pull gather (Eq. cascaded streaming with the wall rules of Sec. 4).
+// Collision in the paper's own form (Sec. 3.1, 3.3): raw moments, the changes
+// of moments g4..g18 of the cascade (Eqs. collision kernel g4 - g18), then
+// f~ = f + K.g with the orthogonal matrix K.  Three corrections to the
+// printed text: K_14 of alpha = 15 is +1 and f~_15 carries +g6 (both from
+// the definitions of K_14 and K_6), the brackets of g15 - g17 close as the
+// relaxation principle requires, and the fourth-order attractor products
+// are divided by rho (unless `literal`).  Any omega_9 and omega_10..18 are
+// allowed.  With a body force the raw moments are those of the half-forced
+// state and the full source (central moments (0, F, 0, ...)) is added.
 // ---------------------------------------------------------------------------
-// Node (x, y, z) receives along e_a the post-collision population that left
-// (x, y, z) - e_a.  If that source lies beyond a bounce-back wall, half-way
-// bounce-back returns the population this node sent toward the wall,
-// d_opp(a)(x) (deviations: w_a = w_opp(a)), plus the moving-wall term when the
-// ghost belongs to the lid plane.
+template <typename T, bool Forced>
+__device__ inline void collide_ghat(T d[Q], const Relax<T> &p, T *omega_out) {
+    const T third = T(1) / T(3);
+    // raw moments of the deviations (rest parts: 1, 1/3 on the diagonal, 1/9
+    // on xxyy, xxzz, yyzz, zero elsewhere)
+    const T Exy = (d[7] + d[10]) + (d[8] + d[9]);
+    const T Exz = (d[11] + d[14]) + (d[12] + d[13]);
+    const T Eyz = (d[15] + d[18]) + (d[16] + d[17]);
+    const T D = d[0] + ((d[1] + d[2]) + (d[3] + d[4]) + (d[5] + d[6])) + (Exy + Exz + Eyz);
+    T Jx = (d[1] - d[2]) + ((d[7] - d[10]) + (d[9] - d[8])) + ((d[11] - d[14]) + (d[13] - d[12]));
+    T Jy = (d[3] - d[4]) + ((d[7] - d[10]) + (d[8] - d[9])) + ((d[15] - d[18]) + (d[17] - d[16]));
+    T Jz = (d[5] - d[6]) + ((d[11] - d[14]) + (d[12] - d[13])) + ((d[15] - d[18]) + (d[16] - d[17]));
+    T kxy = (d[7] + d[10]) - (d[8] + d[9]);
+    T kxz = (d[11] + d[14]) - (d[12] + d[13]);
+    T kyz = (d[15] + d[18]) - (d[16] + d[17]);
+    T kxx = (d[1] + d[2]) + Exy + Exz, kyy = (d[3] + d[4]) + Exy + Eyz, kzz = (d[5] + d[6]) + Exz + Eyz;
+    T kxyy = (d[7] - d[10]) + (d[9] - d[8]), kxxy = (d[7] - d[10]) + (d[8] - d[9]);
+    T kxzz = (d[11] - d[14]) + (d[13] - d[12]), kxxz = (d[11] - d[14]) + (d[12] - d[13]);
+    T kyzz = (d[15] - d[18]) + (d[17] - d[16]), kyyz = (d[15] - d[18]) + (d[16] - d[17]);
+    T kxxyy = Exy, kxxzz = Exz, kyyzz = Eyz;
+
+    const T rho = T(1) + D;
+    const T irho = fast_rcp(rho);
+    T fx = T(0), fy = T(0), fz = T(0);
+    if (Forced) {
+        fx = p.force[0]; fy = p.force[1]; fz = p.force[2];
+        Jx += T(0.5) * fx; Jy += T(0.5) * fy; Jz += T(0.5) * fz;
+    }
+    const T ux = Jx * irho, uy = Jy * irho, uz = Jz * irho;
+    const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+    // source raw moments F . grad_u(u^mnp) (zero unless forced)
+    T sxy = T(0), sxz = T(0), syz = T(0), sxx = T(0), syy = T(0), szz = T(0);
+    T sxyy = T(0), sxzz = T(0), sxxy = T(0), syzz = T(0), sxxz = T(0), syyz = T(0);
+    T sxxyy = T(0), sxxzz = T(0), syyzz = T(0);
+    if (Forced) {
+        sxy = fx * uy + fy * ux; sxz = fx * uz + fz * ux; syz = fy * uz + fz * uy;
+        sxx = T(2) * fx * ux; syy = T(2) * fy * uy; szz = T(2) * fz * uz;
+        sxyy = fx * uy2 + T(2) * fy * ux * uy; sxxy = T(2) * fx * ux * uy + fy * ux2;
+        sxzz = fx * uz2 + T(2) * fz * ux * uz; sxxz = T(2) * fx * ux * uz + fz * ux2;
+        syzz = fy * uz2 + T(2) * fz * uy * uz; syyz = T(2) * fy * uy * uz + fz * uy2;
+        sxxyy = T(2) * (fx * ux * uy2 + fy * ux2 * uy);
+        sxxzz = T(2) * (fx * ux * uz2 + fz * ux2 * uz);
+        syyzz = T(2) * (fy * uy * uz2 + fz * uy2 * uz);
+        kxy += T(0.5) * sxy; kxz += T(0.5) * sxz; kyz += T(0.5) * syz;
+        kxx += T(0.5) * sxx; kyy += T(0.5) * syy; kzz += T(0.5) * szz;
+        kxyy += T(0.5) * sxyy; kxxy += T(0.5) * sxxy; kxzz += T(0.5) * sxzz;
+        kxxz += T(0.5) * sxxz; kyzz += T(0.5) * syzz; kyyz += T(0.5) * syyz;
+        kxxyy += T(0.5) * sxxyy; kxxzz += T(0.5) * sxxzz; kyyzz += T(0.5) * syyzz;
+    }
+    // full raw second moments kxx + 1/3, ...
+    const T Kxx = third + kxx, Kyy = third + kyy, Kzz = third + kzz;
+
+    // non-equilibrium moments (Sec. 3.2) and the local omega^nu
+    const T m4 = kxy - rho * ux * uy, m5 = kxz - rho * ux * uz, m6 = kyz - rho * uy * uz;
+    const T m7 = (kxx - kyy) - rho * (ux2 - uy2), m8 = (kxx - kzz) - rho * (ux2 - uz2);
+    const T m9 = (kxx + kyy + kzz) - (rho * (ux2 + uy2 + uz2) + D);
+    const T a = T(3) * (m7 * m7 - m7 * m8 + m8 * m8) + T(9) * (m4 * m4 + m5 * m5 + m6 * m6);
+    const T b = T(1.5) * p.omega_bulk * p.omega_bulk * m9 * m9;
+    const T om = fast_rcp(solve_tau(p, rho, a, b));
+    if (omega_out) *omega_out = om;
+    const T w9 = p.omega_bulk;
+    const T w10 = p.omega_high[0], w11 = p.omega_high[1], w12 = p.omega_high[2], w13 = p.omega_high[3];
+    const T w14 = p.omega_high[4], w15 = p.omega_high[5], w16 = p.omega_high[6], w17 = p.omega_high[7];
+    const T w18 = p.omega_high[8];
+
+    // second order (Eqs. g4 - g9)
+    const T g4 = om * T(0.25) * (-kxy + rho * ux * uy);
+    const T g5 = om * T(0.25) * (-kxz + rho * ux * uz);
+    const T g6 = om * T(0.25) * (-kyz + rho * uy * uz);
+    const T g7 = om * (T(1) / T(12)) * (-(kxx - kyy) + rho * (ux2 - uy2));
+    const T g8 = om * (T(1) / T(36)) * (-(kxx + kyy - T(2) * kzz) + rho * (ux2 + uy2 - T(2) * uz2));
+    const T g9 = w9 * (T(1) / T(126)) * (-(kxx + kyy + kzz) + rho * (ux2 + uy2 + uz2) + D);
+    // third order (Eqs. g10 - g15)
+    const T q8 = T(0.125), q34 = T(0.75);
+    const T g10 = w10 * q8 * (-(kxyy + kxzz) + T(2) * (uy * kxy + uz * kxz) + ux * (Kyy + Kzz) -
+                              T(2) * rho * ux * (uy2 + uz2)) +
+                  (uy * g4 + uz * g5) + q34 * ux * (-(g7 + g8) + T(14) * g9);
+    const T g11 = w11 * q8 * (-(kyzz + kxxy) + T(2) * (ux * kxy + uz * kyz) + uy * (Kxx + Kzz) -
+                              T(2) * rho * uy * (ux2 + uz2)) +
+                  (ux * g4 + uz * g6) + q34 * uy * (g7 - g8 + T(14) * g9);
+    const T g12 = w12 * q8 * (-(kxxz + kyyz) + T(2) * (ux * kxz + uy * kyz) + uz * (Kxx + Kyy) -
+                              T(2) * rho * uz * (ux2 + uy2)) +
+                  (ux * g5 + uy * g6) + T(1.5) * uz * (g8 + T(7) * g9);
+    const T g13 = w13 * q8 * (-(kxyy - kxzz) + T(2) * (uy * kxy - uz * kxz) + ux * (kyy - kzz) -
+                              T(2) * rho * ux * (uy2 - uz2)) +
+                  (uy * g4 - uz * g5) + q34 * ux * (-g7 + T(3) * g8);
+    const T g14 = w14 * q8 * (-(kyzz - kxxy) + T(2) * (uz * kyz - ux * kxy) + uy * (kzz - kxx) -
+                              T(2) * rho * uy * (uz2 - ux2)) +
+                  (-ux * g4 + uz * g6) + q34 * uy * (-g7 - T(3) * g8);
+    const T g15 = w15 * q8 * (-(kxxz - kyyz) + T(2) * (ux * kxz - uy * kyz) + uz * (kxx - kyy) -
+                              T(2) * rho * uz * (ux2 - uy2)) +
+                  (ux * g5 - uy * g6) + T(1.5) * uz * g7;
+    // post-collision second-order central moments (moments of K.g)
+    const T txx = (kxx - rho * ux2) + T(6) * g7 + T(6) * g8 + T(42) * g9;
+    const T tyy = (kyy - rho * uy2) - T(6) * g7 + T(6) * g8 + T(42) * g9;
+    const T tzz = (kzz - rho * uz2) - T(12) * g8 + T(42) * g9;
+    // attractor products minus their rest values
+    const T pxy = (txx + tyy) * third + txx * tyy;
+    const T pxz = (txx + tzz) * third + txx * tzz;
+    const T pyz = (tyy + tzz) * third + tyy * tzz;
+    T A16, A17, A18;
+    if (p.literal) {
+        A16 = pxy + pxz + pyz;
+        A17 = pxy + pxz - T(2) * pyz;
+        A18 = pxy - pxz;
+    } else {
+        A16 = (pxy + pxz + pyz - D * third) * irho;
+        A17 = (pxy + pxz - T(2) * pyz) * irho;
+        A18 = (pxy - pxz) * irho;
+    }
+    // fourth order (Eqs. g16 - g18); raw fourth moments enter as deviations
+    const T uxuy = ux * uy, uxuz = ux * uz, uyuz = uy * uz;
+    const T g16 = w16 * (T(1) / T(12)) *
+                      (-(kxxyy + kxxzz + kyyzz) + T(2) * ux * (kxyy + kxzz) + T(2) * uy * (kxxy + kyzz) +
+                       T(2) * uz * (kxxz + kyyz) - ux2 * (Kyy + Kzz) - uy2 * (Kzz + Kxx) - uz2 * (Kxx + Kyy) -
+                       T(4) * (uxuy * kxy + uxuz * kxz + uyuz * kyz) +
+                       T(3) * rho * (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) + A16) -
+                  (T(4) / T(3)) * (uxuy * g4 + uxuz * g5 + uyuz * g6) + T(0.5) * (ux2 - uy2) * g7 +
+                  T(0.5) * (ux2 + uy2 - T(2) * uz2) * g8 + (-T(7) * (ux2 + uy2 + uz2) - T(8)) * g9 +
+                  (T(4) / T(3)) * (ux * g10 + uy * g11 + uz * g12);
+    const T g17 = w17 * (T(1) / T(24)) *
+                      (-(kxxyy + kxxzz - T(2) * kyyzz) +
+                       T(2) * (ux * kxyy + ux * kxzz + uy * kxxy + uz * kxxz - T(2) * (uy * kyzz + uz * kyyz)) -
+                       ux2 * (Kyy + Kzz) - uy2 * (Kxx - T(2) * Kzz) - uz2 * (Kxx - T(2) * Kyy) -
+                       T(4) * (uxuy * kxy + uxuz * kxz - T(2) * uyuz * kyz) + A17 +
+                       T(3) * rho * (ux2 * uy2 + ux2 * uz2 - T(2) * uy2 * uz2)) -
+                  (T(2) / T(3)) * (uxuy * g4 + uxuz * g5) + (T(4) / T(3)) * uyuz * g6 +
+                  T(0.25) * (ux2 - uy2 - T(3) * uz2 - T(2)) * g7 + T(0.25) * (ux2 - T(5) * uy2 + uz2 - T(2)) * g8 +
+                  T(1.75) * (-T(2) * ux2 + uy2 + uz2) * g9 + (T(2) / T(3)) * ux * g10 -
+                  third * (uy * g11 + uz * g12) - uy * g14 + uz * g15;
+    const T g18 = w18 * q8 *
+                      (-(kxxyy - kxxzz) + T(2) * (ux * kxyy - ux * kxzz + uy * kxxy - uz * kxxz) -
+                       ux2 * (Kyy - Kzz) - uy2 * Kxx + uz2 * Kxx - T(4) * (uxuy * kxy - uxuz * kxz) + A18 +
+                       T(3) * rho * (ux2 * uy2 - ux2 * uz2)) -
+                  T(2) * uxuy * g4 + T(2) * uxuz * g5 + q34 * (ux2 - uy2 + uz2 + T(2) / T(3)) * g7 +
+                  q34 * (-T(3) * ux2 - uy2 + uz2 - T(2)) * g8 + T(5.25) * (-uy2 + uz2) * g9 + uy * g11 -
+                  uz * g12 + T(2) * ux * g13 - uy * g14 - uz * g15;
+
+    // f~ = f + K.g (Eq. post-collision distribution functions)
+    const T c9 = T(8) * g9 + g16;
+    d[0] += T(12) * g16 - T(30) * g9;
+    {
+        const T s = g7 + g8 - T(11) * g9 - T(4) * (g16 + g17);
+        d[1] += s - T(4) * g10;
+        d[2] += s + T(4) * g10;
+    }
+    {
+        const T s = -g7 + g8 - T(11) * g9 - T(4) * g16 + T(2) * (g17 - g18);
+        d[3] += s - T(4) * g11;
+        d[4] += s + T(4) * g11;
+    }
+    {
+        const T s = -T(2) * g8 - T(11) * g9 - T(4) * g16 + T(2) * (g17 + g18);
+        d[5] += s - T(4) * g12;
+        d[6] += s + T(4) * g12;
+    }
+    {
+        const T s = T(2) * g8 + c9 + g17 + g18;
+        d[7] += s + g4 + g10 + g11 + g13 - g14;
+        d[8] += s - g4 - g10 + g11 - g13 - g14;
+        d[9] += s - g4 + g10 - g11 + g13 + g14;
+        d[10] += s + g4 - g10 - g11 - g13 + g14;
+    }
+    {
+        const T s = g7 - g8 + c9 + g17 - g18;
+        d[11] += s + g5 + g10 + g12 - g13 + g15;
+        d[12] += s - g5 - g10 + g12 + g13 + g15;
+        d[13] += s - g5 + g10 - g12 - g13 - g15;
+        d[14] += s + g5 - g10 - g12 + g13 - g15;
+    }
+    {
+        const T s = -g7 - g8 + c9 - T(2) * g17;
+        d[15] += s + g6 + g11 + g12 + g14 - g15;
+        d[16] += s - g6 - g11 + g12 - g14 - g15;
+        d[17] += s - g6 + g11 - g12 + g14 + g15;
+        d[18] += s + g6 - g11 - g12 - g14 + g15;
+    }
+    if (Forced)
+        add_raw_moment_change<T>(d, T(0), fx, fy, fz, sxy, sxz, syz, sxx, syy, szz, sxyy, sxzz, sxxy, syzz,
+                                 sxxz, syyz, sxxyy, sxxzz, syyzz);
+}
+
+// ---------------------------------------------------------------------------
 // Pull along one direction with the full wall logic (used for lanes on the
 // lattice edge): periodic wrap, half-way bounce-back, moving lid.
 template <typename S, typename T>
@@ -376,19 +577,18 @@ __device__ inline T pull_edge(const S *__restrict__ A, const Geom &g, const Rela
                               int z, uint32_t self) {
     const int ex = cx(a), ey = cy(a), ez = cz(a);
     int sx = x - ex, sy = y - ey, sz = z - ez;
+    // the ghost lies in the lid plane when its coordinate along the lid axis
+    // is just beyond the lid face (edges and corners of that plane included)
+    const int m = g.lid_mask;
+    const bool in_lid = ((m & 1) && sx == -1) || ((m & 2) && sx == g.nx) || ((m & 4) && sy == -1) ||
+                        ((m & 8) && sy == g.ny) || ((m & 16) && sz == -1) || ((m & 32) && sz == g.nz);
     bool wall = false;
     if (sx < 0 || sx >= g.nx) { if (g.px) sx = sx < 0 ? sx + g.nx : sx - g.nx; else wall = true; }
     if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
     if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
     if (!wall) return (T)Plane<S>::load(A, g, a, (uint32_t)(sx + g.nx * sy + g.nxy * sz));
     T v = (T)Plane<S>::load(A, g, opp(a), self);
-    if (g.lid_axis >= 0) {
-        // the ghost lies in the lid plane when the source coordinate along the
-        // lid axis is just beyond the lid face
-        const int sc = g.lid_axis == 0 ? x - ex : (g.lid_axis == 1 ? y - ey : z - ez);
-        const int nmax = g.lid_axis == 0 ? g.nx : (g.lid_axis == 1 ? g.ny : g.nz);
-        if ((g.lid_side > 0 && sc == nmax) || (g.lid_side < 0 && sc == -1)) v += p.lidc[a];
-    }
+    if (in_lid) v += (T)weight(a) * (T(ex) * p.lid6[0] + T(ey) * p.lid6[1] + T(ez) * p.lid6[2]);
     return v;
 }
 

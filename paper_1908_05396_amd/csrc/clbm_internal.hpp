@@ -30,9 +30,19 @@ struct StepLaunch {
 constexpr int kReduceSlots = 9;
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, const StepLaunch &c, hipStream_t st);
+                       const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
 hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, hipStream_t st);
+                       const Relax<float> &pf, bool forced, int route, hipStream_t st);
+
+// Collision forms: 0 = central-moment form for omega_9..18 = 1, 1 = the
+// paper's printed changes of moments g4..g18 with f~ = f + K.g.
+template <typename T, bool Forced, int Route>
+__device__ inline void collide(T d[Q], const Relax<T> &p, T *omega_out) {
+    if constexpr (Route == 0)
+        collide_unit_high<T, Forced>(d, p, omega_out);
+    else
+        collide_ghat<T, Forced>(d, p, omega_out);
+}
 hipError_t launch_macroscopic(int storage, const void *A, double *rho, double *u, const Geom &g,
                               const double *F, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st);

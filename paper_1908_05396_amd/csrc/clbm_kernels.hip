@@ -18,7 +18,7 @@ namespace clbm {
 // are dispatched round-robin to the eight XCDs; with `remap` set, workgroup b
 // takes the tile (b mod 8) * (B/8) + b / 8, so each XCD sweeps a contiguous
 // slab and the neighbour rows a node pulls from sit in the same L2.
-template <typename S, typename T, bool Forced, int LdAux, int StAux>
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, LaunchGrid L) {
     uint32_t b = blockIdx.x;
@@ -33,7 +33,7 @@ stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<
     const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
     T d[Q];
     gather<S, T, LdAux>(A, g, p, x, y, z, self, d);
-    collide_unit_high<T, Forced>(d, p, nullptr);
+    collide<T, Forced, Route>(d, p, nullptr);
 #pragma unroll
     for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B, g, a, self, d[a]);
 }
@@ -42,7 +42,7 @@ stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<
 // Collide-only initialisation from FP64 populations (unpadded planes); a
 // NULL source means the rest state f = w.
 // ---------------------------------------------------------------------------
-template <typename S, typename T, bool Forced>
+template <typename S, typename T, bool Forced, int Route>
 __global__ void __launch_bounds__(256)
 init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Relax<T> p) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
@@ -51,7 +51,7 @@ init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Re
     T d[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
-    collide_unit_high<T, Forced>(d, p, nullptr);
+    collide<T, Forced, Route>(d, p, nullptr);
 #pragma unroll
     for (int a = 0; a < Q; ++a) Plane<S>::store(B, g, a, (uint32_t)i, d[a]);
 }
@@ -187,26 +187,28 @@ reduce_final_kernel(const double *__restrict__ partials, int nblocks, double *__
 // ---------------------------------------------------------------------------
 // Plain streaming copy (bandwidth reference)
 // ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256)
-copy_probe_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+copy_probe_kernel(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st) {
     const int64_t n = (int64_t)(bytes / 16);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (const float4 *)src,
-                       (float4 *)dst, n);
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (const f32x4 *)src,
+                       (f32x4 *)dst, n);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <typename S, typename T, bool Forced>
+template <typename S, typename T, bool Forced, int Route>
 static hipError_t launch_step_f(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
                                 hipStream_t st) {
     LaunchGrid L;
@@ -217,49 +219,67 @@ static hipError_t launch_step_f(const void *A, void *B, const Geom &g, const Rel
     L.aligned = nb & ~7u;
     L.remap = c.xcd_remap;
     dim3 grid(nb), block(c.bx, c.by);
+    const S *a = (const S *)A;
+    S *b = (S *)B;
+    if (Route == 1) {   // the printed form: only the store hint is tunable
+        if (c.nt_stores)
+            hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2, Route>), grid, block, 0, st, a, b, g, p, L);
+        else
+            hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0, Route>), grid, block, 0, st, a, b, g, p, L);
+        return hipGetLastError();
+    }
     const int mode = (c.nt_loads ? 1 : 0) | (c.nt_stores ? 2 : 0);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
-    case 1: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 0>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
-    case 2: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
-    default: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 2>), grid, block, 0, st, (const S *)A, (S *)B, g, p, L); break;
+    case 0: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0, Route>), grid, block, 0, st, a, b, g, p, L); break;
+    case 1: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 0, Route>), grid, block, 0, st, a, b, g, p, L); break;
+    case 2: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2, Route>), grid, block, 0, st, a, b, g, p, L); break;
+    default: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 2, Route>), grid, block, 0, st, a, b, g, p, L); break;
     }
     return hipGetLastError();
 }
 
 template <typename S, typename T>
-static hipError_t launch_step_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced,
+static hipError_t launch_step_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
                                 const StepLaunch &c, hipStream_t st) {
-    return forced ? launch_step_f<S, T, true>(A, B, g, p, c, st) : launch_step_f<S, T, false>(A, B, g, p, c, st);
+    if (route == 0)
+        return forced ? launch_step_f<S, T, true, 0>(A, B, g, p, c, st) : launch_step_f<S, T, false, 0>(A, B, g, p, c, st);
+    return forced ? launch_step_f<S, T, true, 1>(A, B, g, p, c, st) : launch_step_f<S, T, false, 1>(A, B, g, p, c, st);
 }
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, const StepLaunch &c, hipStream_t st) {
+                       const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_step_t<double, double>(A, B, g, pd, forced, c, st);
-    case 1: return launch_step_t<float, float>(A, B, g, pf, forced, c, st);
-    default: return launch_step_t<__half, float>(A, B, g, pf, forced, c, st);
+    case 0: return launch_step_t<double, double>(A, B, g, pd, forced, route, c, st);
+    case 1: return launch_step_t<float, float>(A, B, g, pf, forced, route, c, st);
+    default: return launch_step_t<__half, float>(A, B, g, pf, forced, route, c, st);
     }
 }
 
 template <typename S, typename T>
-static hipError_t launch_init_t(const double *f0, void *B, const Geom &g, const Relax<T> &p, bool forced,
+static hipError_t launch_init_t(const double *f0, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
                                 hipStream_t st) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     dim3 grid((unsigned)((N + 255) / 256)), block(256);
-    if (forced)
-        hipLaunchKernelGGL((init_collide_kernel<S, T, true>), grid, block, 0, st, f0, (S *)B, g, p);
-    else
-        hipLaunchKernelGGL((init_collide_kernel<S, T, false>), grid, block, 0, st, f0, (S *)B, g, p);
+    if (route == 0) {
+        if (forced)
+            hipLaunchKernelGGL((init_collide_kernel<S, T, true, 0>), grid, block, 0, st, f0, (S *)B, g, p);
+        else
+            hipLaunchKernelGGL((init_collide_kernel<S, T, false, 0>), grid, block, 0, st, f0, (S *)B, g, p);
+    } else {
+        if (forced)
+            hipLaunchKernelGGL((init_collide_kernel<S, T, true, 1>), grid, block, 0, st, f0, (S *)B, g, p);
+        else
+            hipLaunchKernelGGL((init_collide_kernel<S, T, false, 1>), grid, block, 0, st, f0, (S *)B, g, p);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, hipStream_t st) {
+                       const Relax<float> &pf, bool forced, int route, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_init_t<double, double>(f0, B, g, pd, forced, st);
-    case 1: return launch_init_t<float, float>(f0, B, g, pf, forced, st);
-    default: return launch_init_t<__half, float>(f0, B, g, pf, forced, st);
+    case 0: return launch_init_t<double, double>(f0, B, g, pd, forced, route, st);
+    case 1: return launch_init_t<float, float>(f0, B, g, pf, forced, route, st);
+    default: return launch_init_t<__half, float>(f0, B, g, pf, forced, route, st);
     }
 }
 

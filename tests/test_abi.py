@@ -78,6 +78,7 @@ def test_buffer_size_padding(clbm, storage, esize):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("K", 0.0), ("K", float("nan")), ("n", -1.0), ("nu_min", 0.0), ("nu_max", 1e-6),
     ("omega_bulk", 2.0), ("rho_wall", 0.0), ("storage", 7), ("lid_face", 9), ("attractor_literal", 2),
+    ("collision", 3), ("plane_pad", -2),
 ])
 def test_invalid_parameters_rejected(clbm, field, value):
     p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")
