@@ -190,6 +190,63 @@ clbm_status clbm_destroy(clbm_lattice *h);
 /* Message for the last failing call on this thread ("" if none). */
 const char *clbm_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent lattices (uneven sizes, Re, n, lids, forces)
+ * advanced together, one persistent launch per time step whose workgroups
+ * stride over the tiles of all instances; k steps are captured into a
+ * hipGraph and replayed.  All instances share the storage type.  Instance i
+ * occupies 19 planes (clbm_buffer_size of its params) at a 256-byte-aligned
+ * offset of each pool, in instance order.
+ * ------------------------------------------------------------------------ */
+typedef struct clbm_batch clbm_batch;
+
+typedef struct {
+    int32_t bx, by;            /* tile: bx consecutive nodes of one z layer (x fastest), a multiple
+                                  of 64, <= 512 (<= 256 for FP64); by must be 1 */
+    int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu x 256 workgroups (1..64) */
+    int32_t graph_steps;       /* steps per captured graph (0: plain launches) */
+} clbm_batch_config;
+
+/* Bytes each of the two pools must hold for these instances. */
+clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *bytes_each);
+
+/* Create a batch over two caller-owned pools.  Validates every instance
+ * (EINVAL, with the instance index in the message); allocates the instance
+ * descriptors, the tile table and reduction scratch; reads the tuned launch
+ * configuration from tune_cache_path (nullable) when it holds an entry for
+ * exactly this set of instances. */
+clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool_a, void *pool_b,
+                              size_t bytes_each, const char *tune_cache_path, clbm_batch **out);
+
+clbm_status clbm_batch_init_rest(clbm_batch *b, void *stream);
+clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0_dev, void *stream);
+
+/* Advance every instance by nsteps: one launch per step over all tiles,
+ * replayed from captured graphs in chunks of graph_steps. */
+clbm_status clbm_batch_step(clbm_batch *b, int64_t nsteps, void *stream);
+
+/* Reference path with the same results: one single-lattice launch per
+ * instance per step. */
+clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream);
+
+clbm_status clbm_batch_macroscopic(clbm_batch *b, int32_t i, double *rho_dev, double *u_dev, void *stream);
+clbm_status clbm_batch_populations(clbm_batch *b, int32_t i, double *f_dev, void *stream);
+
+/* FP64 reductions of clbm_reduce for every instance: out[8*i + k]
+ * (synchronizes; EUNSTABLE if any instance holds non-finite values). */
+clbm_status clbm_batch_reduce(clbm_batch *b, double *out, void *stream);
+
+/* Time candidate launch configurations on the current state (each trial
+ * writes only the spare pool, so the state is unchanged), keep the fastest,
+ * and append it to the tune cache when one was given.  `best` (nullable)
+ * receives it; `best_ms` (nullable) its time per step. */
+clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *best, double *best_ms);
+
+clbm_status clbm_batch_set_config(clbm_batch *b, const clbm_batch_config *cfg);
+clbm_status clbm_batch_get_config(clbm_batch *b, clbm_batch_config *cfg);
+clbm_status clbm_batch_state(clbm_batch *b, int *buffer_index, int64_t *steps_done);
+clbm_status clbm_batch_destroy(clbm_batch *b);
+
 /* Measurement utility: copy `bytes` (a multiple of 16) from src to dst
  * (device memory, 16-byte aligned, not overlapping) with a plain streaming
  * kernel.  Gives the achievable HBM bandwidth of the device and the

@@ -53,6 +53,11 @@ class Launch(ctypes.Structure):
                 ("nt_loads", ctypes.c_int32), ("nt_stores", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
+
+
 _lib = None
 
 #: every function the header declares, with (restype, argtypes)
@@ -79,6 +84,21 @@ SIGNATURES = {
     "clbm_version": (ctypes.c_char_p, []),
     "clbm_lattice_tables": (ctypes.c_int, [_I32P, _I32P, _DP]),
     "clbm_copy_probe": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "clbm_batch_size": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "clbm_batch_create": (ctypes.c_int, [_PP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, ctypes.c_char_p,
+                                         ctypes.POINTER(_VP)]),
+    "clbm_batch_init_rest": (ctypes.c_int, [_VP, _VP]),
+    "clbm_batch_init_populations": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "clbm_batch_step": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
+    "clbm_batch_step_each": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
+    "clbm_batch_macroscopic": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "clbm_batch_populations": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "clbm_batch_reduce": (ctypes.c_int, [_VP, _DP, _VP]),
+    "clbm_batch_autotune": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(BatchConfig), _DP]),
+    "clbm_batch_set_config": (ctypes.c_int, [_VP, ctypes.POINTER(BatchConfig)]),
+    "clbm_batch_get_config": (ctypes.c_int, [_VP, ctypes.POINTER(BatchConfig)]),
+    "clbm_batch_state": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int), _I64P]),
+    "clbm_batch_destroy": (ctypes.c_int, [_VP]),
 }
 
 
@@ -277,3 +297,114 @@ class Lattice:
         bx, by = ctypes.c_int32(), ctypes.c_int32()
         _check(load().clbm_get_block(self._h, ctypes.byref(bx), ctypes.byref(by)))
         return bx.value, by.value
+
+
+class Batch:
+    """Many lattices (one problem description each, shared storage type)
+    stepped together by the batched persistent launch."""
+
+    def __init__(self, specs, storage: str = "f32", device="cuda", track_residual: bool = False,
+                 tune_cache: str = None, collision: str = "auto"):
+        lib = load()
+        self.specs = list(specs)
+        self.storage = storage
+        n = len(self.specs)
+        arr = (Params * n)()
+        for i, sp in enumerate(self.specs):
+            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision)
+        self._params = arr
+        nbytes = ctypes.c_size_t()
+        _check(lib.clbm_batch_size(arr, n, ctypes.byref(nbytes)))
+        self.nbytes = int(nbytes.value)
+        self.device = torch.device(device)
+        self.pools = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        h = ctypes.c_void_p()
+        _check(lib.clbm_batch_create(arr, n, ctypes.c_void_p(self.pools[0].data_ptr()),
+                                     ctypes.c_void_p(self.pools[1].data_ptr()), ctypes.c_size_t(self.nbytes),
+                                     tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def count(self) -> int:
+        return len(self.specs)
+
+    @property
+    def nodes(self) -> int:
+        return sum(s.nx * s.ny * s.nz for s in self.specs)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().clbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_rest(self, stream=None):
+        _check(load().clbm_batch_init_rest(self._h, _stream(stream)))
+
+    def init_populations(self, i: int, f0: torch.Tensor, stream=None):
+        sp = self.specs[i]
+        f0 = f0.to(device=self.device, dtype=torch.float64).contiguous()
+        assert f0.numel() == Q * sp.nx * sp.ny * sp.nz
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(load().clbm_batch_init_populations(self._h, int(i), ctypes.c_void_p(f0.data_ptr()), _stream(s)))
+        if s != torch.cuda.current_stream(self.device):
+            f0.record_stream(s)
+
+    def step(self, nsteps: int, stream=None):
+        _check(load().clbm_batch_step(self._h, int(nsteps), _stream(stream)))
+
+    def step_each(self, nsteps: int, stream=None):
+        _check(load().clbm_batch_step_each(self._h, int(nsteps), _stream(stream)))
+
+    def macroscopic(self, i: int, stream=None):
+        sp = self.specs[i]
+        shape = (sp.nz, sp.ny, sp.nx)
+        rho = torch.empty(shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + shape, dtype=torch.float64, device=self.device)
+        _check(load().clbm_batch_macroscopic(self._h, int(i), ctypes.c_void_p(rho.data_ptr()),
+                                             ctypes.c_void_p(u.data_ptr()), _stream(stream)))
+        return rho, u
+
+    def populations(self, i: int, stream=None):
+        sp = self.specs[i]
+        f = torch.empty((Q, sp.nz, sp.ny, sp.nx), dtype=torch.float64, device=self.device)
+        _check(load().clbm_batch_populations(self._h, int(i), ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+        return f
+
+    def reduce(self, stream=None, raise_unstable: bool = True):
+        out = (ctypes.c_double * (8 * self.count))()
+        rc = load().clbm_batch_reduce(self._h, out, _stream(stream))
+        if rc != CLBM_OK and not (rc == CLBM_EUNSTABLE and not raise_unstable):
+            _check(rc)
+        keys = ("mass", "momentum_x", "momentum_y", "momentum_z", "residual", "nonfinite", "umax", "kinetic")
+        vals = list(out)
+        return [dict(zip(keys, vals[8 * i:8 * i + 8])) for i in range(self.count)]
+
+    def autotune(self, stream=None):
+        c = BatchConfig()
+        ms = ctypes.c_double()
+        _check(load().clbm_batch_autotune(self._h, _stream(stream), ctypes.byref(c), ctypes.byref(ms)))
+        return {k: getattr(c, k) for k, _ in BatchConfig._fields_}, ms.value
+
+    def set_config(self, **kw):
+        c = BatchConfig()
+        _check(load().clbm_batch_get_config(self._h, ctypes.byref(c)))
+        for k, v in kw.items():
+            setattr(c, k, int(v))
+        _check(load().clbm_batch_set_config(self._h, ctypes.byref(c)))
+
+    def get_config(self) -> dict:
+        c = BatchConfig()
+        _check(load().clbm_batch_get_config(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in BatchConfig._fields_}
+
+    def state(self):
+        idx = ctypes.c_int()
+        steps = ctypes.c_int64()
+        _check(load().clbm_batch_state(self._h, ctypes.byref(idx), ctypes.byref(steps)))
+        return idx.value, steps.value

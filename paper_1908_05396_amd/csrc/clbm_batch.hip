@@ -1,0 +1,592 @@
+// Batched stepping of many independent lattices (declared in clbm.h).
+//
+// Every instance keeps its own geometry, power-law parameters, lid and
+// force; all share the storage type.  One persistent launch per time step
+// covers the tiles of all instances: workgroup b processes tiles b, b + G,
+// b + 2G, ... of a flattened tile list, each tile being (instance, z layer,
+// run of bx consecutive nodes of that layer in x-fastest order), so small
+// lattices leave no lanes idle except at the end of a layer.  k consecutive
+// steps are captured into a hipGraph on a library stream and replayed on the
+// caller's stream.
+#include <algorithm>
+#include <vector>
+
+#include "clbm_host.hpp"
+
+namespace clbm {
+
+template <typename T> struct BatchInst {
+    Geom g;
+    Relax<T> p;
+    int64_t base;       // element offset of the instance's first plane in each pool
+    uint32_t tile0;     // first tile of the instance in the flattened list
+    uint32_t chunks;    // tiles per z layer
+    float inv_nx;       // 1 / nx, for the row of a node within a layer
+    int32_t forced;
+};
+
+template <typename S, typename T, int Route>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
+                  const int32_t *__restrict__ tile_inst, uint32_t ntiles) {
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int i = tile_inst[t];
+        const Geom g = inst[i].g;
+        const int64_t base = inst[i].base;
+        const uint32_t local = t - inst[i].tile0;
+        const uint32_t chunks = inst[i].chunks;
+        const int z = (int)(local / chunks);
+        const uint32_t l = (local - (uint32_t)z * chunks) * blockDim.x + threadIdx.x;   // node within the layer
+        if (l >= (uint32_t)g.nxy) continue;
+        // row y = l / nx: float estimate, corrected to the exact quotient
+        int y = (int)((float)l * inst[i].inv_nx);
+        if ((uint32_t)y * (uint32_t)g.nx > l) --y;
+        if ((uint32_t)(y + 1) * (uint32_t)g.nx <= l) ++y;
+        const int x = (int)(l - (uint32_t)y * (uint32_t)g.nx);
+        const Relax<T> &p = inst[i].p;
+        const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
+        T d[Q];
+        gather<S, T, 0>(A + base, g, p, x, y, z, self, d);
+        if (inst[i].forced)
+            collide<T, true, Route>(d, p, nullptr);
+        else
+            collide<T, false, Route>(d, p, nullptr);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) Plane<S, 2>::store(B + base, g, a, self, d[a]);
+    }
+}
+
+template <typename S, typename T>
+static hipError_t launch_batch_t(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
+                                 int route, dim3 grid, dim3 block, hipStream_t st) {
+    if (route == 0)
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 0>), grid, block, 0, st, (const S *)A, (S *)B,
+                           (const BatchInst<T> *)inst, tiles, ntiles);
+    else
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 1>), grid, block, 0, st, (const S *)A, (S *)B,
+                           (const BatchInst<T> *)inst, tiles, ntiles);
+    return hipGetLastError();
+}
+
+static hipError_t launch_batch(int storage, const void *A, void *B, const void *inst, const int32_t *tiles,
+                               uint32_t ntiles, int route, dim3 grid, dim3 block, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, grid, block, st);
+    case 1: return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, grid, block, st);
+    default: return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, grid, block, st);
+    }
+}
+
+static uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
+    const unsigned char *c = (const unsigned char *)data;
+    for (size_t k = 0; k < n; ++k) { h ^= c[k]; h *= 1099511628211ull; }
+    return h;
+}
+
+}  // namespace clbm
+
+using namespace clbm;
+
+struct clbm_batch {
+    int count;
+    int storage;
+    int route;
+    std::vector<clbm_params> prm;
+    std::vector<Geom> geom;
+    std::vector<Relax<double>> rd;
+    std::vector<Relax<float>> rf;
+    std::vector<int64_t> base;      // element offsets
+    std::vector<int> forced;
+    void *pool[2];
+    size_t bytes_each;
+    int cur;
+    bool initialized;
+    int64_t steps_done;
+    clbm_batch_config cfg;
+    int num_cus;
+    // device tables
+    void *d_inst;
+    int32_t *d_tiles;
+    size_t tile_cap;
+    uint32_t ntiles;
+    // reductions
+    double *partials;
+    int nblocks_max;
+    double *results;
+    double *host_results;
+    std::vector<float *> snapshot;
+    std::vector<char> have_snapshot;
+    // graphs
+    hipStream_t cap_stream;
+    hipGraphExec_t exec[2];
+    int exec_steps[2];
+    std::string cache_path;
+    std::string cache_key;
+};
+
+namespace {
+
+size_t instance_bytes(const clbm_params *p) {
+    return (size_t)plane_stride_of(p) * Q * elem_bytes(p->storage);
+}
+
+void drop_graphs(clbm_batch *b) {
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        b->exec[k] = nullptr;
+        b->exec_steps[k] = 0;
+    }
+}
+
+int max_threads(const clbm_batch *b) { return b->storage == CLBM_F64 ? 256 : 512; }
+
+clbm_status check_config(const clbm_batch *b, const clbm_batch_config *c) {
+    const int mt = max_threads(b);
+    if (c->bx < 64 || c->by != 1 || c->bx > mt || c->bx % 64 != 0)
+        return fail(CLBM_EINVAL, "batch tile %d x %d: need by = 1 and bx a multiple of 64, <= %d", c->bx, c->by, mt);
+    if (c->blocks_per_cu < 1 || c->blocks_per_cu > 64) return fail(CLBM_EINVAL, "blocks_per_cu must lie in 1..64");
+    if (c->graph_steps < 0 || c->graph_steps > 4096) return fail(CLBM_EINVAL, "graph_steps must lie in 0..4096");
+    return CLBM_OK;
+}
+
+// Rebuild the flattened tile list and the instance descriptors for a tile shape.
+template <typename T>
+clbm_status upload_tables_t(clbm_batch *b, const std::vector<Relax<T>> &relax) {
+    std::vector<BatchInst<T>> inst(b->count);
+    std::vector<int32_t> tiles;
+    uint64_t total = 0;
+    for (int i = 0; i < b->count; ++i) {
+        const Geom &g = b->geom[i];
+        BatchInst<T> &d = inst[i];
+        memset(&d, 0, sizeof(d));
+        d.g = g;
+        d.p = relax[i];
+        d.base = b->base[i];
+        d.chunks = (uint32_t)((g.nxy + b->cfg.bx - 1) / b->cfg.bx);
+        d.inv_nx = 1.0f / (float)g.nx;
+        d.tile0 = (uint32_t)total;
+        d.forced = b->forced[i];
+        total += (uint64_t)d.chunks * (uint64_t)g.nz;
+    }
+    if (total > 0x7fffffffull) return fail(CLBM_EINVAL, "batch has more than 2^31 tiles");
+    tiles.resize(total);
+    for (int i = 0; i < b->count; ++i) {
+        const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz;
+        std::fill(tiles.begin() + inst[i].tile0, tiles.begin() + inst[i].tile0 + n, i);
+    }
+    if (total > b->tile_cap) {
+        if (b->d_tiles) (void)hipFree(b->d_tiles);
+        b->d_tiles = nullptr;
+        HIP_TRY(hipMalloc((void **)&b->d_tiles, sizeof(int32_t) * total), "batch: tile table");
+        b->tile_cap = total;
+    }
+    HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice), "batch: tiles");
+    HIP_TRY(hipMemcpy(b->d_inst, inst.data(), sizeof(BatchInst<T>) * b->count, hipMemcpyHostToDevice),
+            "batch: descriptors");
+    b->ntiles = (uint32_t)total;
+    drop_graphs(b);
+    return CLBM_OK;
+}
+
+clbm_status upload_tables(clbm_batch *b) {
+    return b->storage == CLBM_F64 ? upload_tables_t<double>(b, b->rd) : upload_tables_t<float>(b, b->rf);
+}
+
+hipError_t launch_one_step(clbm_batch *b, int from, hipStream_t st) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)b->cfg.blocks_per_cu * b->num_cus,
+                                                       std::max<uint32_t>(b->ntiles, 1u));
+    return launch_batch(b->storage, b->pool[from], b->pool[1 - from], b->d_inst, b->d_tiles, b->ntiles, b->route,
+                        dim3(grid), dim3(b->cfg.bx), st);
+}
+
+clbm_status build_graph(clbm_batch *b, int parity) {
+    const int k = b->cfg.graph_steps;
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "batch: begin capture");
+    int c = parity;
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < k && e == hipSuccess; ++s) {
+        e = launch_one_step(b, c, b->cap_stream);
+        c = 1 - c;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(e, "batch: capture launch");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "batch: end capture");
+    e = hipGraphInstantiate(&b->exec[parity], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "batch: instantiate graph");
+    b->exec_steps[parity] = k;
+    return CLBM_OK;
+}
+
+std::string make_cache_key(const clbm_batch *b) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &b->storage, sizeof(b->storage));
+    h = fnv1a(h, &b->route, sizeof(b->route));
+    h = fnv1a(h, &b->count, sizeof(b->count));
+    for (int i = 0; i < b->count; ++i) {
+        const int32_t dims[3] = {b->prm[i].nx, b->prm[i].ny, b->prm[i].nz};
+        h = fnv1a(h, dims, sizeof(dims));
+    }
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+    return arch + "-" + buf;
+}
+
+bool read_cache(clbm_batch *b, clbm_batch_config *out) {
+    if (b->cache_path.empty()) return false;
+    FILE *fh = fopen(b->cache_path.c_str(), "r");
+    if (!fh) return false;
+    char key[256];
+    clbm_batch_config c;
+    bool found = false;
+    while (fscanf(fh, "%255s %d %d %d %d", key, &c.bx, &c.by, &c.blocks_per_cu, &c.graph_steps) == 5) {
+        if (b->cache_key == key && check_config(b, &c) == CLBM_OK) {
+            *out = c;
+            found = true;       // the last entry for a key wins
+        }
+    }
+    fclose(fh);
+    return found;
+}
+
+void append_cache(clbm_batch *b, const clbm_batch_config &c, double ms) {
+    if (b->cache_path.empty()) return;
+    FILE *fh = fopen(b->cache_path.c_str(), "a");
+    if (!fh) return;
+    fprintf(fh, "%s %d %d %d %d\n", b->cache_key.c_str(), c.bx, c.by, c.blocks_per_cu, c.graph_steps);
+    (void)ms;
+    fclose(fh);
+}
+
+clbm_status check_index(clbm_batch *b, int32_t i) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    if (i < 0 || i >= b->count) return fail(CLBM_EINVAL, "instance %d out of range 0..%d", i, b->count - 1);
+    return CLBM_OK;
+}
+
+const char *storage_ptr(clbm_batch *b, int buf, int32_t i) {
+    return (const char *)b->pool[buf] + (size_t)b->base[i] * elem_bytes(b->storage);
+}
+
+}  // namespace
+
+extern "C" {
+
+clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *bytes_each) {
+    if (!inst || count < 1) return fail(CLBM_EINVAL, "need at least one instance");
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        clbm_status st = validate(&inst[i]);
+        if (st != CLBM_OK) return fail(st, "instance %d: %s", i, g_err.c_str());
+        if (inst[i].storage != inst[0].storage) return fail(CLBM_EINVAL, "instance %d: storage differs", i);
+        // the row of a node within its layer comes from a float estimate with
+        // one correction, exact while a layer has at most 2^22 nodes
+        if ((int64_t)inst[i].nx * inst[i].ny > ((int64_t)1 << 22))
+            return fail(CLBM_EINVAL, "instance %d: a z layer of more than 2^22 nodes", i);
+        total += instance_bytes(&inst[i]);
+    }
+    if (bytes_each) *bytes_each = total;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool_a, void *pool_b,
+                              size_t bytes_each, const char *tune_cache_path, clbm_batch **out) {
+    if (!out) return fail(CLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    clbm_status st = clbm_batch_size(inst, count, &need);
+    if (st != CLBM_OK) return st;
+    if (!pool_a || !pool_b || pool_a == pool_b) return fail(CLBM_EINVAL, "need two distinct pools");
+    if (!aligned256(pool_a) || !aligned256(pool_b)) return fail(CLBM_EINVAL, "pools must be 256-byte aligned");
+    if (bytes_each < need) return fail(CLBM_EINVAL, "pools hold %zu bytes, need %zu", bytes_each, need);
+
+    clbm_batch *b = new clbm_batch();
+    b->count = count;
+    b->storage = inst[0].storage;
+    b->route = 0;
+    for (int i = 0; i < count; ++i)
+        if (route_of(&inst[i]) == 1) b->route = 1;   // one form for the whole batch
+    if (b->route == 0)
+        for (int i = 0; i < count; ++i)
+            if (inst[i].collision == CLBM_COLLIDE_GHAT) b->route = 1;
+    int64_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        b->prm.push_back(inst[i]);
+        b->geom.push_back(make_geom(&inst[i]));
+        b->rd.push_back(make_relax<double>(&inst[i]));
+        b->rf.push_back(make_relax<float>(&inst[i]));
+        b->base.push_back(off);
+        b->forced.push_back(inst[i].force[0] != 0.0 || inst[i].force[1] != 0.0 || inst[i].force[2] != 0.0);
+        off += plane_stride_of(&inst[i]) * Q;
+    }
+    b->pool[0] = pool_a;
+    b->pool[1] = pool_b;
+    b->bytes_each = bytes_each;
+    b->cfg.bx = 256;
+    b->cfg.by = 1;
+    b->cfg.blocks_per_cu = 8;
+    b->cfg.graph_steps = 20;
+    b->num_cus = 256;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        b->num_cus = cus;
+    b->cache_path = tune_cache_path ? tune_cache_path : "";
+    b->cache_key = make_cache_key(b);
+    clbm_batch_config cached;
+    if (read_cache(b, &cached)) b->cfg = cached;
+
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    const size_t inst_size = b->storage == CLBM_F64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
+    if (e == hipSuccess) e = hipMalloc(&b->d_inst, inst_size * count);
+    int64_t maxn = 0;
+    for (int i = 0; i < count; ++i) maxn = std::max<int64_t>(maxn, (int64_t)b->geom[i].n);
+    b->nblocks_max = (int)std::min<int64_t>(1024, (maxn + kReduceThreads - 1) / kReduceThreads);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->partials, sizeof(double) * kReduceSlots * b->nblocks_max);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->results, sizeof(double) * kReduceSlots * count);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&b->host_results, sizeof(double) * kReduceSlots * count, hipHostMallocDefault);
+    b->snapshot.assign(count, nullptr);
+    b->have_snapshot.assign(count, 0);
+    for (int i = 0; i < count && e == hipSuccess; ++i)
+        if (inst[i].track_residual) e = hipMalloc((void **)&b->snapshot[i], sizeof(float) * 3 * b->geom[i].n);
+    if (e != hipSuccess) {
+        clbm_batch_destroy(b);
+        return hip_fail(e, "clbm_batch_create: allocation");
+    }
+    st = upload_tables(b);
+    if (st != CLBM_OK) {
+        clbm_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_destroy(clbm_batch *b) {
+    if (!b) return CLBM_OK;
+    drop_graphs(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->partials) (void)hipFree(b->partials);
+    if (b->results) (void)hipFree(b->results);
+    if (b->host_results) (void)hipHostFree(b->host_results);
+    for (float *s : b->snapshot)
+        if (s) (void)hipFree(s);
+    delete b;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_init_rest(clbm_batch *b, void *stream) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    for (int i = 0; i < b->count; ++i)
+        HIP_TRY(launch_init(b->storage, nullptr, (void *)storage_ptr(b, 0, i), b->geom[i], b->rd[i], b->rf[i],
+                            b->forced[i], b->route, (hipStream_t)stream),
+                "clbm_batch_init_rest");
+    b->cur = 0;
+    b->initialized = true;
+    b->steps_done = 0;
+    std::fill(b->have_snapshot.begin(), b->have_snapshot.end(), 0);
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0, void *stream) {
+    clbm_status st = check_index(b, i);
+    if (st != CLBM_OK) return st;
+    if (!f0) return fail(CLBM_EINVAL, "f0 is NULL");
+    if (!b->initialized) return fail(CLBM_ESTATE, "initialise the batch with clbm_batch_init_rest first");
+    HIP_TRY(launch_init(b->storage, f0, (void *)storage_ptr(b, b->cur, i), b->geom[i], b->rd[i], b->rf[i],
+                        b->forced[i], b->route, (hipStream_t)stream),
+            "clbm_batch_init_populations");
+    b->have_snapshot[i] = 0;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_step(clbm_batch *b, int64_t nsteps, void *stream) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
+    if (!b->initialized) return fail(CLBM_ESTATE, "clbm_batch_step before an init call");
+    hipStream_t st = (hipStream_t)stream;
+    const int k = b->cfg.graph_steps;
+    while (k > 0 && nsteps >= k) {
+        if (!b->exec[b->cur] || b->exec_steps[b->cur] != k) {
+            clbm_status s = build_graph(b, b->cur);
+            if (s != CLBM_OK) return s;
+        }
+        HIP_TRY(hipGraphLaunch(b->exec[b->cur], st), "clbm_batch_step: graph launch");
+        if (k & 1) b->cur = 1 - b->cur;
+        b->steps_done += k;
+        nsteps -= k;
+    }
+    for (; nsteps > 0; --nsteps) {
+        HIP_TRY(launch_one_step(b, b->cur, st), "clbm_batch_step");
+        b->cur = 1 - b->cur;
+        b->steps_done++;
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
+    if (!b->initialized) return fail(CLBM_ESTATE, "clbm_batch_step_each before an init call");
+    hipStream_t st = (hipStream_t)stream;
+    for (; nsteps > 0; --nsteps) {
+        for (int i = 0; i < b->count; ++i) {
+            StepLaunch c;
+            const int nx = b->geom[i].nx;
+            c.bx = nx >= 256 ? 256 : (nx >= 64 ? 64 * (nx / 64) : nx);
+            if (c.bx > 256) c.bx = 256;
+            c.by = 1;
+            while (c.bx * c.by * 2 <= 256 && c.by * 2 <= b->geom[i].ny) c.by *= 2;
+            c.xcd_remap = 0;
+            c.nt_loads = 0;
+            c.nt_stores = 1;
+            HIP_TRY(launch_step(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
+                                b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
+                    "clbm_batch_step_each");
+        }
+        b->cur = 1 - b->cur;
+        b->steps_done++;
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_macroscopic(clbm_batch *b, int32_t i, double *rho, double *u, void *stream) {
+    clbm_status st = check_index(b, i);
+    if (st != CLBM_OK) return st;
+    if (!b->initialized) return fail(CLBM_ESTATE, "clbm_batch_macroscopic before an init call");
+    if (!rho && !u) return CLBM_OK;
+    HIP_TRY(launch_macroscopic(b->storage, storage_ptr(b, b->cur, i), rho, u, b->geom[i], b->prm[i].force,
+                               (hipStream_t)stream),
+            "clbm_batch_macroscopic");
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_populations(clbm_batch *b, int32_t i, double *f, void *stream) {
+    clbm_status st = check_index(b, i);
+    if (st != CLBM_OK) return st;
+    if (!f) return fail(CLBM_EINVAL, "output is NULL");
+    if (!b->initialized) return fail(CLBM_ESTATE, "clbm_batch_populations before an init call");
+    HIP_TRY(launch_export(b->storage, storage_ptr(b, b->cur, i), f, b->geom[i], (hipStream_t)stream),
+            "clbm_batch_populations");
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_reduce(clbm_batch *b, double *out, void *stream) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    if (!out) return fail(CLBM_EINVAL, "out is NULL");
+    if (!b->initialized) return fail(CLBM_ESTATE, "clbm_batch_reduce before an init call");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < b->count; ++i) {
+        const int nb = (int)std::min<int64_t>(b->nblocks_max, ((int64_t)b->geom[i].n + kReduceThreads - 1) /
+                                                                   kReduceThreads);
+        HIP_TRY(launch_reduce(b->storage, storage_ptr(b, b->cur, i), b->snapshot[i], b->have_snapshot[i] ? 1 : 0,
+                              b->geom[i], b->prm[i].force, b->partials, nb, b->results + (size_t)kReduceSlots * i,
+                              st),
+                "clbm_batch_reduce");
+    }
+    HIP_TRY(hipMemcpyAsync(b->host_results, b->results, sizeof(double) * kReduceSlots * b->count,
+                           hipMemcpyDeviceToHost, st),
+            "clbm_batch_reduce: copy");
+    HIP_TRY(hipStreamSynchronize(st), "clbm_batch_reduce: sync");
+    double bad = 0.0;
+    for (int i = 0; i < b->count; ++i) {
+        const double *r = b->host_results + (size_t)kReduceSlots * i;
+        double *o = out + 8 * (size_t)i;
+        o[0] = (double)b->geom[i].n + r[0];
+        o[1] = r[1]; o[2] = r[2]; o[3] = r[3];
+        o[4] = (b->snapshot[i] && b->have_snapshot[i] && r[5] > 0.0) ? sqrt(r[4] / r[5]) : 0.0;
+        o[5] = r[6];
+        o[6] = r[7];
+        o[7] = r[8];
+        if (b->snapshot[i]) b->have_snapshot[i] = 1;
+        bad += r[6];
+    }
+    if (bad > 0.0) return fail(CLBM_EUNSTABLE, "%.0f nodes hold non-finite populations", bad);
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_set_config(clbm_batch *b, const clbm_batch_config *c) {
+    if (!b || !c) return fail(CLBM_EINVAL, "NULL argument");
+    clbm_status st = check_config(b, c);
+    if (st != CLBM_OK) return st;
+    const bool tiles_change = c->bx != b->cfg.bx || c->by != b->cfg.by;
+    b->cfg = *c;
+    drop_graphs(b);
+    return tiles_change ? upload_tables(b) : CLBM_OK;
+}
+
+clbm_status clbm_batch_get_config(clbm_batch *b, clbm_batch_config *c) {
+    if (!b || !c) return fail(CLBM_EINVAL, "NULL argument");
+    *c = b->cfg;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_state(clbm_batch *b, int *buffer_index, int64_t *steps_done) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    if (buffer_index) *buffer_index = b->cur;
+    if (steps_done) *steps_done = b->steps_done;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *best, double *best_ms) {
+    if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
+    if (!b->initialized) return fail(CLBM_ESTATE, "autotune needs an initialised state");
+    hipStream_t st = (hipStream_t)stream;
+    static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
+    static const int bpcs[] = {2, 4, 8, 16};
+    const clbm_batch_config keep = b->cfg;
+    clbm_batch_config win = keep;
+    double win_ms = 1e300;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "autotune: event");
+    HIP_TRY(hipEventCreate(&e1), "autotune: event");
+    clbm_status result = CLBM_OK;
+    for (const auto &sh : shapes) {
+        clbm_batch_config c = keep;
+        c.bx = sh[0];
+        c.by = sh[1];
+        if (check_config(b, &c) != CLBM_OK) continue;
+        for (int bpc : bpcs) {
+            c.blocks_per_cu = bpc;
+            if ((result = clbm_batch_set_config(b, &c)) != CLBM_OK) break;
+            // trials read the state and write the spare pool: the state is unchanged
+            hipError_t e = launch_one_step(b, b->cur, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_one_step(b, b->cur, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { result = hip_fail(e, "autotune: trial"); break; }
+            if (ms / 5.0 < win_ms) { win_ms = ms / 5.0; win = c; }
+        }
+        if (result != CLBM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != CLBM_OK) {
+        clbm_batch_set_config(b, &keep);
+        return result;
+    }
+    result = clbm_batch_set_config(b, &win);
+    if (result != CLBM_OK) return result;
+    append_cache(b, win, win_ms);
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return CLBM_OK;
+}
+
+}  // extern "C"

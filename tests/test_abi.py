@@ -106,3 +106,20 @@ def test_create_rejects_bad_buffers(clbm):
     # too small
     assert lib.clbm_create(ctypes.byref(p), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 16,
                            ctypes.byref(h)) == clbm.CLBM_EINVAL
+
+
+def test_batch_size_validates_each_instance(clbm):
+    specs = [W.cavity(8, 0.05, 1.0, 10.0), W.cavity(12, 0.05, 0.7, 10.0)]
+    arr = (clbm.Params * 2)()
+    for i, sp in enumerate(specs):
+        arr[i] = clbm.params_from_spec(sp, "f32")
+    n = ctypes.c_size_t()
+    assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == 0
+    assert n.value == sum(clbm.buffer_size(arr[i])[1] for i in range(2))
+    arr[1].storage = 0
+    assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
+    assert "instance 1" in clbm.load().clbm_last_error().decode()
+    arr[1] = clbm.params_from_spec(specs[1], "f32")
+    arr[1].K = -1.0
+    assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
+    assert clbm.load().clbm_batch_size(arr, 0, ctypes.byref(n)) == clbm.CLBM_EINVAL

@@ -1,0 +1,137 @@
+"""Batched persistent stepping (many lattices in one launch per step, graph
+replay, autotuned tiles) against the oracle and against the one-launch-per-
+instance reference path."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clbm():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05396_amd import clbm as c
+    c.load()
+    return c
+
+
+def _mixed_specs():
+    return [
+        W.cavity(12, 0.05, 0.6, 50.0, name="b_cav12"),
+        W.cavity(16, 0.05, 1.4, 80.0, name="b_cav16").with_(nx=70, ny=9, name="b_cav70x9x16"),
+        W.poiseuille(6, 20, 5, n=0.8, Re=10.0, umax=0.02, name="b_chan"),
+        W.LatticeSpec(nx=9, ny=11, nz=7, K=0.02, n=1.0, periodic=(1, 1, 1), force=(2e-5, -1e-5, 0.0),
+                      name="b_periodic"),
+    ]
+
+
+# the fully periodic box has no walls to drive it: a larger perturbation
+# keeps its velocities well above the FP64 noise floor
+EPS = [1e-3, 1e-3, 1e-3, 5e-2]
+
+
+def test_batch_matches_oracle_per_instance(clbm):
+    specs = _mixed_specs()
+    steps = 70
+    b = clbm.Batch(specs, storage="f64")
+    b.init_rest()
+    for i, sp in enumerate(specs):
+        b.init_populations(i, W.perturbed_populations(sp, 40 + i, EPS[i], device="cuda"))
+    b.set_config(graph_steps=20)
+    b.step(steps)          # three graph replays and ten plain launches
+    torch.cuda.synchronize()
+    for i, sp in enumerate(specs):
+        print(f"[gpu] batch instance {i} {sp.name}", flush=True)
+        _, u = b.macroscopic(i)
+        f = oracle.run(sp, W.perturbed_populations(sp, 40 + i, EPS[i]).numpy(), steps)
+        _, u_ref = oracle.macroscopic(sp, f)
+        err = np.abs(u.cpu().numpy() - u_ref).max() / np.abs(u_ref).max()
+        assert err < 1e-12, (sp.name, err)
+
+
+# The batch kernel and the single-lattice kernel inline the same collision
+# code but may contract multiply-adds differently, so they agree to rounding
+# rather than bit for bit: a few ulp of the populations (FP32) or of the
+# stored FP16 deviations.
+ATOL = {"f32": 2e-6, "f16": 2e-4}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_equals_per_instance_launches(clbm, storage):
+    specs = _mixed_specs()
+    outs = []
+    for mode in ("batch", "each"):
+        b = clbm.Batch(specs, storage=storage)
+        b.init_rest()
+        for i, sp in enumerate(specs):
+            b.init_populations(i, W.perturbed_populations(sp, 7 + i, 1e-3, device="cuda"))
+        (b.step if mode == "batch" else b.step_each)(33)
+        outs.append([b.populations(i).cpu().numpy() for i in range(len(specs))])
+        assert b.state() == (1, 33)
+        b.close()
+    for x, y in zip(*outs):
+        err = np.abs(x - y).max()
+        print(f"batch vs per-instance {storage}: {err:.3e}")
+        assert err < ATOL[storage]
+
+
+def test_graph_replay_equals_plain_launches(clbm):
+    specs = _mixed_specs()
+    outs = []
+    for k in (0, 8, 9):
+        b = clbm.Batch(specs, storage="f32")
+        b.init_rest()
+        b.set_config(graph_steps=k)
+        b.step(5)
+        b.step(27)
+        b.step(3)
+        outs.append([b.populations(i).cpu().numpy() for i in range(len(specs))])
+    for other in outs[1:]:
+        for x, y in zip(outs[0], other):
+            assert np.array_equal(x, y)
+
+
+def test_autotune_keeps_state_and_caches(clbm, tmp_path):
+    specs = _mixed_specs()
+    cache = str(tmp_path / "tune.txt")
+    b = clbm.Batch(specs, storage="f32", tune_cache=cache)
+    b.init_rest()
+    b.step(10)
+    before = [b.populations(i).cpu().numpy() for i in range(len(specs))]
+    cfg, ms = b.autotune()
+    after = [b.populations(i).cpu().numpy() for i in range(len(specs))]
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert ms > 0 and os.path.exists(cache)
+    b2 = clbm.Batch(specs, storage="f32", tune_cache=cache)
+    assert b2.get_config() == cfg
+    # different instance set: no cached entry applies
+    b3 = clbm.Batch(specs[:2], storage="f32", tune_cache=cache)
+    assert b3.get_config() != cfg or cfg == clbm.Batch(specs[:2], storage="f32").get_config()
+
+
+def test_config4_batch_full_size(clbm):
+    """The 64-cavity batch (edges 32..96, n in [0.4, 1.6], Re in [50, 1000])
+    at full size: the persistent graph-replayed launch agrees with one launch
+    per instance, and every instance keeps its mass (closed cavities)."""
+    specs = W.config_batch()
+    b = clbm.Batch(specs, storage="f32")
+    b.init_rest()
+    r0 = b.reduce()
+    b.autotune()
+    b.step(40)
+    ref = clbm.Batch(specs, storage="f32")
+    ref.init_rest()
+    ref.step_each(40)
+    r1 = b.reduce(raise_unstable=False)
+    for i in range(len(specs)):
+        err = np.abs(b.populations(i).cpu().numpy() - ref.populations(i).cpu().numpy()).max()
+        assert err < ATOL["f32"], (i, err)
+        assert r1[i]["nonfinite"] == 0
+        assert abs(r1[i]["mass"] - r0[i]["mass"]) < 1e-5 * r0[i]["mass"]
