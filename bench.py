@@ -10,8 +10,10 @@ Prints ONE JSON line: MLUPS of the timed region (exactly --steps steps after
 --warmup untimed ones, bracketed by device synchronisation), the roofline of
 the stream-collide kernel (algorithmic bytes per launch / average launch time
 measured with events on the launch stream), the FP16-deviation and FP64
-storage variants of the same workload, the achievable copy bandwidth, and the
-CPU oracle timed on the host cores on a bounded sample of the same workload.
+storage variants of the same workload, the 64-cavity batch (persistent
+graph-replayed launch vs one launch per instance), the achievable copy
+bandwidth, and the CPU oracle timed on the host cores on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -106,6 +108,33 @@ def roofline(storage, nodes, kernel_ms, workload):
             "bytes_per_lup": BYTES_PER_LUP[storage]}
 
 
+def batched(clbm, torch, W, storage, steps):
+    """The 64-cavity batch: one persistent launch per step (graph-replayed,
+    autotuned) against one launch per instance per step."""
+    specs = W.config_batch()
+    nodes = sum(s.nodes for s in specs)
+    b = clbm.Batch(specs, storage=storage)
+    b.init_rest()
+    b.step(10)
+    cfg, _ = b.autotune()
+    out = {"workload": "batch64_cavities_L32-96_n0.4-1.6_re50-1000", "instances": len(specs), "nodes": nodes,
+           "storage": storage, "steps": steps, "config": cfg}
+    for key, fn in (("mlups", b.step), ("mlups_one_launch_per_instance", b.step_each)):
+        fn(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        out[key] = round(nodes * steps / (time.perf_counter() - t0) / 1e6, 1)
+    out["speedup"] = round(out["mlups"] / out["mlups_one_launch_per_instance"], 3)
+    r = b.reduce(raise_unstable=False)
+    out["nonfinite_instances"] = sum(1 for x in r if x["nonfinite"] > 0)
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(clbm, torch, nbytes=4 << 30, reps=10):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
@@ -161,6 +190,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -217,6 +248,8 @@ def main():
         "mass_drift": main_run["mass_drift"],
         "variants": variants,
     }
+    if not args.no_batch:
+        line["batched"] = batched(clbm, torch, W, "f32", args.batch_steps)
     if not args.no_copy:
         line["copy_gbs"] = round(copy_bandwidth(clbm, torch), 1)
     if not args.no_cpu:
