@@ -2,9 +2,12 @@
 """Throughput benchmark of the D3Q19 cascaded power-law stream-collide step.
 
 Workload (default): lid-driven cubic cavity 512^3 (134.2 M nodes), Re = 3200,
-n = 0.75, lid velocity 0.04, rest start; FP32 storage of f - w with FP32
-arithmetic; the FP64 mass reduction every 100 steps tracks the mass drift.
-One step = one fused pull stream-collide launch over the whole lattice.
+n = 0.75, lid velocity 0.04, rest start, 5000 steps; FP32 storage of f - w
+with FP32 arithmetic; the FP64 mass reduction every 100 steps tracks the mass
+drift.  One step = one fused pull stream-collide launch over the whole lattice.
+The FP16-deviation and FP64 storage runs of the same workload end at the same
+step, and the errors of FP32 and FP16 against FP64 are reported on the
+centrelines u_x(y), u_y(x) and normwise over the whole field.
 
 Prints ONE JSON line: MLUPS of the timed region (exactly --steps steps after
 --warmup untimed ones, bracketed by device synchronisation), the roofline of
@@ -33,7 +36,7 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 BYTES_PER_LUP = {"f64": 304, "f32": 152, "f16": 76}   # 19 reads + 19 writes per node update
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_05396_amd", "csrc", f)
-                  for f in ("clbm_device.hpp", "clbm_kernels.hip")]
+                  for f in ("clbm_device.hpp", "clbm_kernels.hip", "clbm_fused.hip")]
 
 
 def kernel_source_hash() -> str:
@@ -58,9 +61,48 @@ def measured_traffic(storage: str, workload: str):
     return float(m_bytes.group(1))
 
 
-def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None):
-    """Run warmup + timed steps; returns timing and reduction results."""
+def centrelines(u, L):
+    """u_x(y) on x = H/2 and u_y(x) on y = H/2, both in the plane z = H/2; for
+    an even edge length the two middle node columns (planes) are averaged."""
+    c0, c1 = L // 2 - 1, L // 2
+    mid = (u[:, c0] + u[:, c1]) / 2                     # (3, y, x) at z = H/2
+    ux_y = (mid[0, :, c0] + mid[0, :, c1]) / 2
+    uy_x = (mid[1, c0, :] + mid[1, c1, :]) / 2
+    return ux_y, uy_x
+
+
+def accuracy_vs(torch, runs, ref_key, U, L):
+    """Errors of each run's velocity field against the reference run's:
+    centreline max |du| / U and the normwise max |du| / max |u_ref|."""
+    ref = runs[ref_key]
+    rx, ry = centrelines(ref, L)
+    out = {"reference": f"{ref_key} storage on the GPU, same workload and step count"}
+    for key, u in runs.items():
+        if key == ref_key:
+            continue
+        ax, ay = centrelines(u, L)
+        cl = max((ax - rx).abs().max().item(), (ay - ry).abs().max().item()) / U
+        out[key] = {"centreline_max_abs_over_U": float(f"{cl:.3e}"),
+                    "field_normwise": float(f"{((u - ref).abs().max() / ref.abs().max()).item():.3e}")}
+    return out
+
+
+# the launch form the library does not pick by default for a storage type
+OTHER_FORM = "other"
+
+
+def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None, keep_u=False, launch=None):
+    """Run warmup + timed steps; returns timing and reduction results (and
+    the final velocity field, FP64 on the device, if `keep_u`).  `launch`
+    OTHER_FORM switches between one and two steps per launch."""
     lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block)
+    if launch == OTHER_FORM:
+        cur = lat.get_launch()
+        if cur["fuse_steps"] == 1:
+            lat.set_launch(fuse_steps=2, fuse_rows=8 if storage == "f64" else 16,
+                           fuse_planes=min(spec.nz, 32 if storage == "f64" else 8))
+        else:
+            lat.set_launch(fuse_steps=1)
     lat.init_rest()
     r0 = lat.reduce()
     lat.step(warmup)
@@ -88,24 +130,31 @@ def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=
     out = {
         "wall_s": wall,
         "ms_per_step": wall * 1e3 / steps,
-        "kernel_ms_per_launch": kernel_ms / steps,
+        "kernel_ms_per_step": kernel_ms / steps,
         "mass_drift": (r1["mass"] - r0["mass"]) / r0["mass"],
         "umax": r1["umax"],
         "nonfinite": r1["nonfinite"],
         "block": list(lat.get_block()),
+        "launch": lat.get_launch(),
     }
+    if keep_u:
+        out["u"] = lat.macroscopic()[1]
     lat.close()
     del lat
     torch.cuda.empty_cache()
     return out
 
 
-def roofline(storage, nodes, kernel_ms, workload):
-    achieved = BYTES_PER_LUP[storage] * nodes / (kernel_ms * 1e-3) / 1e9
+def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch):
+    """HBM roofline of the stream-collide kernel: algorithmic bytes of one
+    launch (19 reads + 19 writes per node and step, times the steps one
+    launch advances) over the launch's average duration; `traffic` is the
+    measured HBM bytes per launch from the committed counter summary."""
+    achieved = BYTES_PER_LUP[storage] * nodes / (kernel_ms_per_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(storage, workload),
-            "bytes_per_lup": BYTES_PER_LUP[storage]}
+            "bytes_per_lup": BYTES_PER_LUP[storage], "steps_per_launch": steps_per_launch}
 
 
 def batched(clbm, torch, W, storage, steps):
@@ -132,6 +181,35 @@ def batched(clbm, torch, W, storage, steps):
     b.close()
     del b
     torch.cuda.empty_cache()
+    return out
+
+
+def accuracy_run(clbm, torch, spec, steps, report_every):
+    """The same cavity in FP64, FP32 and FP16-deviation storage from rest for
+    `steps` steps; errors of FP32 and FP16 against FP64 on the centrelines."""
+    fields, history = {}, {}
+    for st in ("f64", "f32", "f16"):
+        lat = clbm.Lattice(spec, storage=st, track_residual=True)
+        lat.init_rest()
+        m0 = lat.reduce()["mass"]
+        t0 = time.perf_counter()
+        done, hist = 0, []
+        while done < steps:
+            k = min(report_every, steps - done)
+            lat.step(k)
+            done += k
+            r = lat.reduce(raise_unstable=False)
+            hist.append({"step": done, "umax": r["umax"], "residual": r["residual"],
+                         "mass_drift": (r["mass"] - m0) / m0, "nonfinite": r["nonfinite"]})
+            print(f"[accuracy] {spec.name} {st} step {done}: {time.perf_counter() - t0:.1f} s, "
+                  f"residual {r['residual']:.3e}, umax {r['umax']:.5f}", file=sys.stderr, flush=True)
+        fields[st] = lat.macroscopic()[1]
+        history[st] = hist[-1]
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    out = accuracy_vs(torch, fields, "f64", spec.lid_velocity[0], spec.nx)
+    out.update({"workload": spec.name, "steps": steps, "final": history})
     return out
 
 
@@ -181,17 +259,22 @@ def cpu_baseline(spec_full, min_seconds=10.0, max_seconds=30.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=512, help="cavity edge length")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
     ap.add_argument("--reduce-every", type=int, default=100)
-    ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--variant-steps", type=int, default=-1,
+                    help="steps of the other storage variants (default: --steps + --warmup - 20, so that "
+                         "all storages end at the same step and their velocity fields are compared)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--accuracy256", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: run the 256^3 cavity (Re 1000, n 0.5) for STEPS steps in "
+                         "FP64, FP32 and FP16-deviation storage and print the centreline errors vs FP64")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -207,25 +290,53 @@ def main():
     from paper_1908_05396_amd import clbm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.accuracy256:
+        print(json.dumps(accuracy_run(clbm, torch, W.config_cavity256(), args.accuracy256, 5000)), flush=True)
+        return
     spec = W.config_cavity512() if args.size == 512 else \
         W.cavity(args.size, 0.04, 0.75, 3200.0, name=f"cavity{args.size}_re3200_n0.75")
     workload = spec.name
 
-    main_run = time_lattice(clbm, torch, spec, args.storage, args.steps, args.warmup, args.reduce_every)
+    compare = not args.no_variants and args.variant_steps < 0
+    vsteps = args.steps + args.warmup - 20 if args.variant_steps < 0 else args.variant_steps
+    main_run = time_lattice(clbm, torch, spec, args.storage, args.steps, args.warmup, args.reduce_every,
+                            keep_u=compare)
     mlups = spec.nodes * args.steps / (main_run["ms_per_step"] * args.steps * 1e-3) / 1e6
 
     variants = {}
+    fields = {args.storage: main_run.pop("u", None)}
     if not args.no_variants:
         for st in ("f16", "f64", "f32"):
             if st == args.storage:
                 continue
-            r = time_lattice(clbm, torch, spec, st, args.variant_steps, 20, args.reduce_every)
+            r = time_lattice(clbm, torch, spec, st, vsteps, 20, args.reduce_every, keep_u=compare)
+            fields[st] = r.pop("u", None)
+            spl = r["launch"]["fuse_steps"]
             variants[st] = {
                 "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
-                "roofline": roofline(st, spec.nodes, r["kernel_ms_per_launch"], workload),
-                "kernel_ms_per_launch": round(r["kernel_ms_per_launch"], 4),
-                "mass_drift": r["mass_drift"], "steps": args.variant_steps,
+                "roofline": roofline(st, spec.nodes, r["kernel_ms_per_step"], workload, spl),
+                "kernel_ms_per_launch": round(r["kernel_ms_per_step"] * spl, 4),
+                "steps_per_launch": spl,
+                "mass_drift": r["mass_drift"], "steps": vsteps,
             }
+    # the other launch form of each storage (one vs two steps per launch)
+    launch_forms = {}
+    if not args.no_variants:
+        for st in ("f32", "f64", "f16"):
+            r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, launch=OTHER_FORM)
+            spl = r["launch"]["fuse_steps"]
+            launch_forms[st] = {
+                "launch": r["launch"], "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+                "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
+                "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS, 4)}
+
+    accuracy = None
+    if compare:
+        accuracy = accuracy_vs(torch, fields, "f64", spec.lid_velocity[0], args.size)
+        accuracy["steps"] = args.steps + args.warmup
+    del fields
+    torch.cuda.empty_cache()
 
     line = {
         "metric": "MLUPS & %HBM roofline, D3Q19 cascaded power-law; FP32/FP16-store vs FP64",
@@ -242,11 +353,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "nodes": spec.nodes, "storage": args.storage,
                    "lid_velocity": spec.lid_velocity[0], "Re": 3200.0, "n": spec.n, "K": spec.K,
-                   "init": "rest", "reduce_every": args.reduce_every, "block": main_run["block"]},
-        "roofline": roofline(args.storage, spec.nodes, main_run["kernel_ms_per_launch"], workload),
-        "kernel_ms_per_launch": round(main_run["kernel_ms_per_launch"], 4),
+                   "init": "rest", "reduce_every": args.reduce_every, "launch": main_run["launch"]},
+        "roofline": roofline(args.storage, spec.nodes, main_run["kernel_ms_per_step"], workload,
+                             main_run["launch"]["fuse_steps"]),
+        "kernel_ms_per_launch": round(main_run["kernel_ms_per_step"] * main_run["launch"]["fuse_steps"], 4),
         "mass_drift": main_run["mass_drift"],
         "variants": variants,
+        "other_launch_form": launch_forms,
+        "accuracy": accuracy,
     }
     if not args.no_batch:
         line["batched"] = batched(clbm, torch, W, "f32", args.batch_steps)

@@ -100,7 +100,11 @@ typedef struct {
     double K;                  /* consistency coefficient mu_p > 0 (Eq. 5) */
     double n;                  /* power-law index n > 0 (Eq. 5; n = 1 Newtonian) */
     double nu_min, nu_max;     /* clip of the apparent kinematic viscosity mu/rho,
-                                  0 < nu_min < nu_max */
+                                  0 < nu_min < nu_max; the relaxation rate is then
+                                  1/(3 nu_max + 1/2) <= omega <= 1/(3 nu_min + 1/2).  Rates
+                                  near 2 at the lid corners of shear-thinning cavities at
+                                  Re ~ 10^3 make the scheme diverge; the default caps omega
+                                  at 1.95 */
     double omega_bulk;         /* omega_9 in (0, 2); the paper uses 1 */
     double omega_high[9];      /* omega_10 .. omega_18 in (0, 2); the paper uses 1 */
     double force[3];           /* body force per unit volume (0: unforced kernel) */
@@ -112,7 +116,7 @@ typedef struct clbm_lattice clbm_lattice;
 
 /* Defaults: 1x1x1, no periodic axis, no lid, FP32 storage, normalized
  * attractors, residual tracking on, default plane padding, automatic
- * collision form, K = 0.01, n = 1, viscosity clip for omega in [0.1, 1.99],
+ * collision form, K = 0.01, n = 1, viscosity clip for omega in [0.1, 1.95],
  * omega_bulk = omega_high = 1, no force, rho_wall = 1. */
 clbm_status clbm_params_default(clbm_params *p);
 
@@ -169,12 +173,20 @@ clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done);
 /* Launch configuration of the stream-collide kernel (results do not depend
  * on it; only speed does). */
 typedef struct {
-    int32_t bx, by;      /* threads per block along x and y: bx*by a multiple of 64, at most
-                            512 (FP32/FP16 storage) or 256 (FP64) */
+    int32_t bx, by;      /* threads per block along x and y: bx*by at most 512 (FP32/FP16
+                            storage) or 256 (FP64); whole 64-lane waves run fastest */
     int32_t xcd_remap;   /* 1: workgroup b takes tile (b mod 8)*(B/8) + b/8, so each of the
                             eight XCDs sweeps a contiguous slab of the lattice */
     int32_t nt_loads;    /* 1: non-temporal hint on population loads */
     int32_t nt_stores;   /* 1: non-temporal hint on population stores */
+    int32_t fuse_steps;  /* time steps per launch: 1, or 2 (temporal blocking: a workgroup
+                            computes the first step on a 64 x fuse_rows patch of columns plus
+                            its one-node ring, keeps it on chip and writes the second step of
+                            the inner 62 x (fuse_rows - 2) columns, marching along z; the
+                            result equals two one-step launches).  clbm_step runs an odd
+                            remainder as one one-step launch */
+    int32_t fuse_rows;   /* rows of a two-step workgroup, ring included: 8 or 16 (FP64: 8) */
+    int32_t fuse_planes; /* output z planes per two-step workgroup, >= 1 */
     int32_t reserved;    /* must be 0 */
 } clbm_launch;
 

@@ -4,14 +4,16 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libclbm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("clbm_api.hip", "clbm_kernels.hip", "clbm_batch.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f)
+           for f in ("clbm_api.hip", "clbm_kernels.hip", "clbm_fused.hip", "clbm_batch.hip")]
 
 # Packed FP32 instructions are disabled for every device compilation.
-HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-command-line-argument"]
 
@@ -22,12 +24,30 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] + SOURCES + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    """Compile each source to an object (in parallel), then link the library."""
+    tag = ".tmp%d" % os.getpid()
+    objs = [os.path.join(HERE, "csrc", os.path.basename(src) + tag + ".o") for src in SOURCES]
+    cmds = [[hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+            for src, obj in zip(SOURCES, objs)]
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            for cmd in cmds:
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+            for r in ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+                if r.returncode != 0:
+                    sys.stderr.write(r.stdout + r.stderr)
+                    raise subprocess.CalledProcessError(r.returncode, r.args)
+        tmp = LIB + tag
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
+        os.replace(tmp, LIB)
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     return LIB
 
 

@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("nt_loads", ctypes.c_int32), ("nt_stores", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("nt_loads", ctypes.c_int32), ("nt_stores", ctypes.c_int32), ("fuse_steps", ctypes.c_int32),
+                ("fuse_rows", ctypes.c_int32), ("fuse_planes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BatchConfig(ctypes.Structure):

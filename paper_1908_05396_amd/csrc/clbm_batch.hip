@@ -453,6 +453,9 @@ clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream) {
             c.xcd_remap = 0;
             c.nt_loads = 0;
             c.nt_stores = 1;
+            c.fuse_steps = 1;
+            c.fuse_rows = 8;
+            c.fuse_planes = 1;
             HIP_TRY(launch_step(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
                                 b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
                     "clbm_batch_step_each");

@@ -570,26 +570,38 @@ __device__ inline void collide_ghat(T d[Q], const Relax<T> &p, T *omega_out) {
 }
 
 // ---------------------------------------------------------------------------
+// Wall rules.  A ghost (source outside the lattice on a non-periodic axis)
+// lies in the lid plane when its coordinate along the lid axis is just beyond
+// the lid face; edges and corners of that plane included.
+__device__ inline bool ghost_in_lid(const Geom &g, int sx, int sy, int sz) {
+    const int m = g.lid_mask;
+    return ((m & 1) && sx == -1) || ((m & 2) && sx == g.nx) || ((m & 4) && sy == -1) ||
+           ((m & 8) && sy == g.ny) || ((m & 16) && sz == -1) || ((m & 32) && sz == g.nz);
+}
+
+// Half-way bounce-back along e_a: the node's own post-collision population
+// opposite to a (w_a = w_opp(a), so the deviation carries over), plus the
+// moving-wall term w_a 6 rho_w (e_a . U_w) for a ghost in the lid plane.
+template <typename T>
+__device__ inline T wall_value(T own_opposite, const Relax<T> &p, int a, bool in_lid) {
+    T v = own_opposite;
+    if (in_lid) v += (T)weight(a) * (T(cx(a)) * p.lid6[0] + T(cy(a)) * p.lid6[1] + T(cz(a)) * p.lid6[2]);
+    return v;
+}
+
 // Pull along one direction with the full wall logic (used for lanes on the
 // lattice edge): periodic wrap, half-way bounce-back, moving lid.
 template <typename S, typename T>
 __device__ inline T pull_edge(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int a, int x, int y,
                               int z, uint32_t self) {
-    const int ex = cx(a), ey = cy(a), ez = cz(a);
-    int sx = x - ex, sy = y - ey, sz = z - ez;
-    // the ghost lies in the lid plane when its coordinate along the lid axis
-    // is just beyond the lid face (edges and corners of that plane included)
-    const int m = g.lid_mask;
-    const bool in_lid = ((m & 1) && sx == -1) || ((m & 2) && sx == g.nx) || ((m & 4) && sy == -1) ||
-                        ((m & 8) && sy == g.ny) || ((m & 16) && sz == -1) || ((m & 32) && sz == g.nz);
+    int sx = x - cx(a), sy = y - cy(a), sz = z - cz(a);
+    const bool in_lid = ghost_in_lid(g, sx, sy, sz);
     bool wall = false;
     if (sx < 0 || sx >= g.nx) { if (g.px) sx = sx < 0 ? sx + g.nx : sx - g.nx; else wall = true; }
     if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
     if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
     if (!wall) return (T)Plane<S>::load(A, g, a, (uint32_t)(sx + g.nx * sy + g.nxy * sz));
-    T v = (T)Plane<S>::load(A, g, opp(a), self);
-    if (in_lid) v += (T)weight(a) * (T(ex) * p.lid6[0] + T(ey) * p.lid6[1] + T(ez) * p.lid6[2]);
-    return v;
+    return wall_value<T>((T)Plane<S>::load(A, g, opp(a), self), p, a, in_lid);
 }
 
 // Pull gather (Eq. cascaded streaming with the wall rules of Sec. 4).  Node

@@ -1,0 +1,229 @@
+// Two time steps per launch: temporal blocking of the pull stream-collide.
+//
+// A workgroup is ROWS waves.  Wave w works on lattice row y0 - 1 + w and lane
+// l on column x0 - 1 + l, so the workgroup covers a 64 x ROWS patch of
+// columns whose inner 62 x (ROWS - 2) columns are its output.  It marches
+// along z through its chunk of output planes [z0, z1).  For plane m it first
+// computes the state after the first step, I(m), at every column of the patch
+// (the ring of halo columns included) exactly as the one-step kernel does
+// (same gather with the wall rules, same collision, rounded to the storage
+// type), and keeps it on chip.  Output plane z = m - 1 then pulls its
+// second-step inputs from I(z - 1), I(z) and I(z + 1) instead of memory,
+// collides and is written.  The result is the state that two one-step
+// launches leave; memory sees one read of the patch (with its halo) and one
+// write per node per two steps.
+//
+// On-chip placement of I(m), by the direction's (e_y, e_z):
+//   e_y = 0   registers of the column's own lane, passed to the x neighbours
+//             by lane shuffles: e_z = 0 {0, 1, 2}, +1 {5, 11, 12}, -1 {6, 13, 14};
+//   e_y != 0  LDS rings indexed by plane: e_z = 0 {3, 4, 7, 8, 9, 10} three
+//             slots, e_z = +1 {15, 16} four slots, e_z = -1 {17, 18} three.
+// A plane's e_z = +1 values are read by the output plane above it, its
+// e_z = -1 values by the plane below, and all of its own-node values serve
+// the bounce-back of the output plane at its own height.  With one barrier per
+// plane, a slot read while producing output z is rewritten no earlier than
+// while producing z + 2, which the ring sizes guarantee.
+#include "clbm_internal.hpp"
+
+namespace clbm {
+
+namespace {
+
+constexpr int kLanes = 64;
+constexpr int kOut = kLanes - 2;    // output columns per wave
+
+// position of an e_y != 0 direction inside its LDS group
+__host__ __device__ constexpr int lds_index(int a) {
+    return a == 3 ? 0 : a == 4 ? 1 : a == 7 ? 2 : a == 8 ? 3 : a == 9 ? 4 : a == 10 ? 5
+         : a == 15 || a == 17 ? 0 : 1;
+}
+// register slot of an e_y = 0 direction inside its e_z class
+__host__ __device__ constexpr int reg_index(int a) { return cx(a) == 0 ? 0 : (cx(a) == 1 ? 1 : 2); }
+
+template <typename S, int ROWS> struct FusedShared {
+    S e0[3][6][ROWS][kLanes];
+    S up[4][2][ROWS][kLanes];
+    S dn[3][2][ROWS][kLanes];
+};
+
+template <typename S, typename T> __device__ inline T round_trip(T v) {
+    return Conv<S, T>::load(Conv<S, T>::store(v));
+}
+
+}  // namespace
+
+struct FusedGrid {
+    uint32_t gx, gy, gz;    // patches along x and y, z chunks
+    int32_t cz;             // output planes per z chunk
+};
+
+template <typename S, typename T, bool Forced, int Route, int ROWS>
+__global__ void __launch_bounds__(kLanes * ROWS)
+stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, FusedGrid L) {
+    __shared__ FusedShared<S, ROWS> sh;
+    const int l = (int)(threadIdx.x & (kLanes - 1));
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
+    uint32_t b = blockIdx.x;
+    const int tx = (int)(b % L.gx);
+    b /= L.gx;
+    const int ty = (int)(b % L.gy);
+    const int tz = (int)(b / L.gy);
+    const int gx = tx * kOut - 1 + l;             // this lane's column (unwrapped)
+    const int gy = ty * (ROWS - 2) - 1 + w;       // this wave's row (unwrapped)
+    const int z0 = tz * L.cz;
+    const int z1 = min(z0 + L.cz, g.nz);
+    const bool out = l >= 1 && l <= kOut && gx < g.nx && w >= 1 && w <= ROWS - 2 && gy < g.ny;
+
+    // First-step column of this lane: needed up to one past the last output
+    // column/row; wrapped on periodic axes; none (a ghost) beyond a wall.
+    int wx = gx, wy = gy;
+    bool col = gx <= min(g.nx, tx * kOut + kOut) && gy <= min(g.ny, ty * (ROWS - 2) + ROWS - 2);
+    if (wx < 0 || wx >= g.nx) { if (g.px) wx = wx < 0 ? wx + g.nx : wx - g.nx; else col = false; }
+    if (wy < 0 || wy >= g.ny) { if (g.py) wy = wy < 0 ? wy + g.ny : wy - g.ny; else col = false; }
+
+    T r0c[3], r0n[3];              // e_z = 0,  e_y = 0 of I(z), I(z + 1)
+    T rpp[3], rpc[3], rpn[3];      // e_z = +1, e_y = 0 of I(z - 1), I(z), I(z + 1)
+    T rmc[3], rmn[3];              // e_z = -1, e_y = 0 of I(z), I(z + 1)
+
+    // I(m) into LDS ring slots (index jm = m - z0 + 1) and the given registers
+    auto first_step = [&](int m, int jm, T (&o0)[3], T (&op)[3], T (&om)[3]) {
+        // The buffer descriptors of the 19 planes are rebuilt from the base
+        // pointer on every plane instead of being kept (and spilled) across
+        // the loop: the empty asm hides the pointer's loop invariance.
+        const S *Am = A;
+        asm volatile("" : "+s"(Am));
+        int wz = m;
+        bool v = col;
+        if (wz < 0 || wz >= g.nz) { if (g.pz) wz = wz < 0 ? wz + g.nz : wz - g.nz; else v = false; }
+        T d[Q];
+        if (v) {
+            const uint32_t self = (uint32_t)wx + (uint32_t)g.nx * (uint32_t)wy + (uint32_t)g.nxy * (uint32_t)wz;
+            gather<S, T, 0>(Am, g, p, wx, wy, wz, self, d);
+            collide<T, Forced, Route>(d, p, nullptr);
+        } else {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) d[a] = T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            if (cy(a) == 0) {
+                const T r = round_trip<S, T>(d[a]);
+                if (cz(a) == 0) o0[reg_index(a)] = r;
+                else if (cz(a) == 1) op[reg_index(a)] = r;
+                else om[reg_index(a)] = r;
+            } else if (cz(a) == 0) {
+                sh.e0[jm % 3][lds_index(a)][w][l] = Conv<S, T>::store(d[a]);
+            } else if (cz(a) == 1) {
+                sh.up[jm % 4][lds_index(a)][w][l] = Conv<S, T>::store(d[a]);
+            } else {
+                sh.dn[jm % 3][lds_index(a)][w][l] = Conv<S, T>::store(d[a]);
+            }
+        }
+    };
+
+    // second step at output plane z (jz = z - z0 + 1 indexes I(z))
+    auto second_step = [&](int z, int jz) {
+        // every lane takes part in the shuffles; lanes 1..62 use them
+        const T n1 = __shfl_up(r0c[1], 1, kLanes), n2 = __shfl_down(r0c[2], 1, kLanes);
+        const T n11 = __shfl_up(rpp[1], 1, kLanes), n12 = __shfl_down(rpp[2], 1, kLanes);
+        const T n13 = __shfl_up(rmn[1], 1, kLanes), n14 = __shfl_down(rmn[2], 1, kLanes);
+        if (!out) return;
+        T d[Q];
+        d[0] = r0c[0]; d[1] = n1; d[2] = n2;
+        d[5] = rpp[0]; d[11] = n11; d[12] = n12;
+        d[6] = rmn[0]; d[13] = n13; d[14] = n14;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            if (cy(a) == 0) continue;
+            const int r = w - cy(a), c = l - cx(a);
+            if (cz(a) == 0) d[a] = Conv<S, T>::load(sh.e0[jz % 3][lds_index(a)][r][c]);
+            else if (cz(a) == 1) d[a] = Conv<S, T>::load(sh.up[(jz + 3) % 4][lds_index(a)][r][c]);
+            else d[a] = Conv<S, T>::load(sh.dn[(jz + 1) % 3][lds_index(a)][r][c]);
+        }
+        const bool xw = !g.px && (gx == 0 || gx == g.nx - 1);
+        const bool yw = !g.py && (gy == 0 || gy == g.ny - 1);
+        const bool zw = !g.pz && (z == 0 || z == g.nz - 1);
+        if (xw || yw || zw) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                const int sx = gx - cx(a), sy = gy - cy(a), sz = z - cz(a);
+                const bool ghost = (!g.px && (sx < 0 || sx >= g.nx)) || (!g.py && (sy < 0 || sy >= g.ny)) ||
+                                   (!g.pz && (sz < 0 || sz >= g.nz));
+                if (!ghost) continue;
+                const int o = opp(a);
+                T own;
+                if (cy(o) == 0)
+                    own = cz(o) == 0 ? r0c[reg_index(o)] : (cz(o) == 1 ? rpc[reg_index(o)] : rmc[reg_index(o)]);
+                else if (cz(o) == 0)
+                    own = Conv<S, T>::load(sh.e0[jz % 3][lds_index(o)][w][l]);
+                else if (cz(o) == 1)
+                    own = Conv<S, T>::load(sh.up[jz % 4][lds_index(o)][w][l]);
+                else
+                    own = Conv<S, T>::load(sh.dn[jz % 3][lds_index(o)][w][l]);
+                d[a] = wall_value<T>(own, p, a, ghost_in_lid(g, sx, sy, sz));
+            }
+        }
+        collide<T, Forced, Route>(d, p, nullptr);
+        S *Bz = B;
+        asm volatile("" : "+s"(Bz));
+        const uint32_t self = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy + (uint32_t)g.nxy * (uint32_t)z;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) Plane<S, 2>::store(Bz, g, a, self, d[a]);
+    };
+
+    // plane m = z0 - 1 .. z1: first step of I(m), then the output plane m - 1
+    for (int m = z0 - 1; m <= z1; ++m) {
+        first_step(m, m - z0 + 1, r0n, rpn, rmn);
+        __syncthreads();
+        if (m > z0) second_step(m - 1, m - z0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            r0c[k] = r0n[k];
+            rpp[k] = rpc[k];
+            rpc[k] = rpn[k];
+            rmc[k] = rmn[k];
+        }
+    }
+}
+
+template <typename S, typename T, bool Forced, int Route, int ROWS>
+static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T> &p, int planes, hipStream_t st) {
+    FusedGrid L;
+    L.gx = (uint32_t)((g.nx + kOut - 1) / kOut);
+    L.gy = (uint32_t)((g.ny + ROWS - 3) / (ROWS - 2));
+    L.cz = planes;
+    L.gz = (uint32_t)((g.nz + planes - 1) / planes);
+    const uint64_t nb = (uint64_t)L.gx * L.gy * L.gz;
+    if (nb == 0 || nb > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS>), dim3((uint32_t)nb), dim3(kLanes * ROWS),
+                       0, st, (const S *)A, (S *)B, g, p, L);
+    return hipGetLastError();
+}
+
+template <typename S, typename T, int ROWS>
+static hipError_t launch2_r(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
+                            int planes, hipStream_t st) {
+    if (route == 0)
+        return forced ? launch2_f<S, T, true, 0, ROWS>(A, B, g, p, planes, st)
+                      : launch2_f<S, T, false, 0, ROWS>(A, B, g, p, planes, st);
+    return forced ? launch2_f<S, T, true, 1, ROWS>(A, B, g, p, planes, st)
+                  : launch2_f<S, T, false, 1, ROWS>(A, B, g, p, planes, st);
+}
+
+hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
+                        const Relax<float> &pf, bool forced, int route, int rows, int planes, hipStream_t st) {
+    if (planes < 1) return hipErrorInvalidValue;
+    switch (storage) {
+    case 0:
+        if (rows != 8) return hipErrorInvalidValue;
+        return launch2_r<double, double, 8>(A, B, g, pd, forced, route, planes, st);
+    case 1:
+        return rows == 16 ? launch2_r<float, float, 16>(A, B, g, pf, forced, route, planes, st)
+                          : launch2_r<float, float, 8>(A, B, g, pf, forced, route, planes, st);
+    default:
+        return rows == 16 ? launch2_r<__half, float, 16>(A, B, g, pf, forced, route, planes, st)
+                          : launch2_r<__half, float, 8>(A, B, g, pf, forced, route, planes, st);
+    }
+}
+
+}  // namespace clbm

@@ -26,11 +26,16 @@ struct StepLaunch {
     int32_t bx, by;         // threads per block along x and y
     int32_t xcd_remap;
     int32_t nt_loads, nt_stores;
+    int32_t fuse_steps;     // 1: one step per launch; 2: two (temporal blocking)
+    int32_t fuse_rows;      // rows per two-step workgroup, halo rows included (8 or 16)
+    int32_t fuse_planes;    // output z planes per two-step workgroup
 };
 constexpr int kReduceSlots = 9;
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                        const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
+hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
+                        const Relax<float> &pf, bool forced, int route, int rows, int planes, hipStream_t st);
 hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
                        const Relax<float> &pf, bool forced, int route, hipStream_t st);
 

@@ -24,8 +24,8 @@ import numpy as np
 #: paper's velocity order; used only to shape perturbed initial states.
 INPUT_WEIGHTS = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=np.float64)
 
-#: default viscosity clip: omega^nu kept in [0.1, 1.99], i.e. nu = (1/omega - 1/2)/3
-NU_MIN_DEFAULT = (1.0 / 1.99 - 0.5) / 3.0
+#: default viscosity clip: omega^nu kept in [0.1, 1.95], i.e. nu = (1/omega - 1/2)/3
+NU_MIN_DEFAULT = (1.0 / 1.95 - 0.5) / 3.0
 NU_MAX_DEFAULT = (1.0 / 0.1 - 0.5) / 3.0
 
 # lid faces
