@@ -30,15 +30,15 @@ struct clbm_lattice {
     bool have_snapshot;
 };
 
-// Default two-step launch (measured on the 512^3 cavity, MI355X): FP64 gains
-// from two steps per launch (rows 8, 32 planes per workgroup); FP32 and FP16
-// run one step per launch, where the halo recomputation costs as much as the
-// saved traffic (FP32) or more (FP16, bound by arithmetic).  The chunk length
-// trades the two ring planes of first-step work per chunk (2/planes) against
-// the number of workgroups in flight.
+// Default launch form (measured on the 512^3 cavity, MI355X, in the developed
+// flow): one step per launch for every storage type.  Two steps per launch
+// halve the state traffic but recompute the first step on the patch ring
+// (18-37% more collisions); FP32 comes out even, FP16 (bound by arithmetic)
+// and FP64 (whose Newton solve dominates once the whole cavity moves) lose.
+// The two-step defaults below are the best measured shapes.
 static void default_fusion(const clbm_params *p, StepLaunch *c) {
     const bool f64 = p->storage == CLBM_F64;
-    c->fuse_steps = f64 ? 2 : 1;
+    c->fuse_steps = 1;
     c->fuse_rows = f64 ? 8 : 16;
     int planes = f64 ? 32 : 8;
     if (planes > p->nz) planes = p->nz;

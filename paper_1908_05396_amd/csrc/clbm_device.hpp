@@ -187,7 +187,26 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
         return p.k < T(0) ? p.tau_max : p.tau_min;
     }
     const T c = p.log2_3K - p.n * fast_log2(rho);
-    T s = clampv(c + p.k * fast_log2(q0), p.s_lo, p.s_hi);   // exact if tau were 1
+    T s;
+    if constexpr (NewtonTol<T>::fixed) {
+        s = clampv(c + p.k * fast_log2(q0), p.s_lo, p.s_hi);   // exact if tau were 1
+    } else {
+        // FP64: the FP32 iteration (hardware transcendentals) gives the root
+        // to ~1e-6; the FP64 steps below then converge in two or three.
+        const float cf = (float)c, kf = (float)p.k, af = (float)a, bf = (float)b;
+        const float lo = (float)p.s_lo, hi = (float)p.s_hi, two_kf = 2.0f * kf;
+        float sf = clampv(cf + kf * fast_log2((float)q0), lo, hi);
+        for (int it = 0; it < NewtonTol<float>::maxit; ++it) {
+            const float e = fast_exp2(sf);
+            const float it1 = fast_rcp(0.5f + e);
+            const float q = af * (it1 * it1) + bf;
+            const float phi = sf - cf - kf * fast_log2(q);
+            const float dphi = 1.0f + two_kf * (1.0f - bf * fast_rcp(q)) * (e * it1);
+            sf = clampv(sf - phi * fast_rcp(dphi), lo, hi);
+        }
+        s = (T)sf;
+        if (!(s == s)) s = clampv(c + p.k * fast_log2(q0), p.s_lo, p.s_hi);   // FP32 range trouble
+    }
     const T two_k = T(2) * p.k;
     bool last = false;
     for (int it = 0; it < NewtonTol<T>::maxit; ++it) {
