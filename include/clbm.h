@@ -185,7 +185,8 @@ typedef struct {
                             the inner 62 x (fuse_rows - 2) columns, marching along z; the
                             result equals two one-step launches).  clbm_step runs an odd
                             remainder as one one-step launch */
-    int32_t fuse_rows;   /* rows of a two-step workgroup, ring included: 8 or 16 (FP64: 8) */
+    int32_t fuse_rows;   /* rows of a two-step workgroup, ring included: 8, 16 (not FP64), or
+                            12 (FP32: the next plane's loads go straight to LDS) */
     int32_t fuse_planes; /* output z planes per two-step workgroup, >= 1 */
     int32_t reserved;    /* must be 0 */
 } clbm_launch;

@@ -265,8 +265,9 @@ clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
         return fail(CLBM_EINVAL, "block %d x %d: need 1 <= bx*by <= %d", c->bx, c->by, maxt);
     if ((c->xcd_remap | c->nt_loads | c->nt_stores) & ~1) return fail(CLBM_EINVAL, "launch flags must be 0 or 1");
     if (c->fuse_steps != 1 && c->fuse_steps != 2) return fail(CLBM_EINVAL, "fuse_steps must be 1 or 2");
-    if (c->fuse_rows != 8 && !(c->fuse_rows == 16 && h->prm.storage != CLBM_F64))
-        return fail(CLBM_EINVAL, "fuse_rows must be 8 or 16 (8 with FP64 storage)");
+    const bool rows_ok = c->fuse_rows == 8 || (c->fuse_rows == 16 && h->prm.storage != CLBM_F64) ||
+                         (c->fuse_rows == 12 && h->prm.storage == CLBM_F32);
+    if (!rows_ok) return fail(CLBM_EINVAL, "fuse_rows must be 8, 16 (not FP64) or 12 (FP32 only)");
     if (c->fuse_planes < 1) return fail(CLBM_EINVAL, "fuse_planes must be >= 1");
     if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
     h->launch.bx = c->bx;

@@ -623,12 +623,42 @@ __device__ inline T pull_edge(const S *__restrict__ A, const Geom &g, const Rela
     return wall_value<T>((T)Plane<S>::load(A, g, opp(a), self), p, a, in_lid);
 }
 
+// Element index within plane a of the interior pull source of node `self`
+// (outside the plane for lanes on the lattice edge, which get the full rule).
+__device__ inline uint32_t pull_offset(const Geom &g, int a, uint32_t self) {
+    return self + (uint32_t)(-(cx(a) + cy(a) * g.nx + cz(a) * g.nxy));
+}
+
+// Lanes on the lattice edge: redo the directions that cross it with the full
+// rule (half-way bounce-back returns d_opp(a)(x) since w_a = w_opp(a), plus
+// the moving-wall term in the lid plane; periodic axes wrap).
+template <typename S, typename T>
+__device__ inline void fix_edges(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
+                                 uint32_t self, T d[Q]) {
+    const bool yz_edge = y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1;
+    if (yz_edge) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+    } else {
+        if (x == 0) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                if (cx(a) == 1) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+        }
+        if (x == g.nx - 1) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                if (cx(a) == -1) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+        }
+    }
+}
+
 // Pull gather (Eq. cascaded streaming with the wall rules of Sec. 4).  Node
 // (x, y, z) receives along e_a the post-collision population that left
 // (x, y, z) - e_a.  Interior lanes read at a uniform offset per direction;
-// lanes on the lattice edge redo the directions that cross it with the full
-// rule (half-way bounce-back returns d_opp(a)(x) since w_a = w_opp(a), plus
-// the moving-wall term in the lid plane; periodic axes wrap).
+// lanes on the lattice edge redo the directions that cross it (fix_edges).
+// (The edge logic is written out here again rather than calling fix_edges:
+// the one-step kernels compile measurably faster code this way.)
 template <typename S, typename T, int LdAux = 0>
 __device__ inline void gather(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
                               uint32_t self, T d[Q]) {

@@ -46,6 +46,22 @@ template <typename S, int ROWS> struct FusedShared {
     S dn[3][2][ROWS][kLanes];
 };
 
+// prefetched first-step inputs of the next plane: one row per wave, each
+// lane's 19 values at its own position (written by direct-to-LDS loads); a
+// separate LDS object, so that reads of the rings need not wait for them
+template <typename S, int ROWS, bool PF> struct FusedInput {
+    S in[PF ? Q : 1][PF ? ROWS : 1][PF ? kLanes : 1];
+};
+
+// s_waitcnt lgkmcnt(0) with vmcnt and expcnt left free (gfx9 encoding)
+constexpr int kWaitLgkmcnt0 = 0xC07F;
+
+// element size of a direct-to-LDS load (allowed: 1, 2, 4, 12, 16 bytes)
+template <typename S, bool PF> struct LdsBytes { static constexpr int value = PF ? (int)sizeof(S) : 4; };
+
+// s_waitcnt vmcnt(0) with the other counters left free (gfx9 encoding)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 template <typename S, typename T> __device__ inline T round_trip(T v) {
     return Conv<S, T>::load(Conv<S, T>::store(v));
 }
@@ -57,10 +73,11 @@ struct FusedGrid {
     int32_t cz;             // output planes per z chunk
 };
 
-template <typename S, typename T, bool Forced, int Route, int ROWS>
+template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF>
 __global__ void __launch_bounds__(kLanes * ROWS)
 stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, FusedGrid L) {
     __shared__ FusedShared<S, ROWS> sh;
+    __shared__ FusedInput<S, ROWS, PF> pf;
     const int l = (int)(threadIdx.x & (kLanes - 1));
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
     uint32_t b = blockIdx.x;
@@ -85,6 +102,29 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
     T rpp[3], rpc[3], rpn[3];      // e_z = +1, e_y = 0 of I(z - 1), I(z), I(z + 1)
     T rmc[3], rmn[3];              // e_z = -1, e_y = 0 of I(z), I(z + 1)
 
+    // Issue the interior pull loads of plane m straight into this wave's row
+    // of sh.in (no registers held while they are in flight).
+    auto prefetch = [&](int m) {
+        if constexpr (PF) {
+            const S *Am = A;
+            asm volatile("" : "+s"(Am));
+            int wz = m;
+            bool v = col;
+            if (wz < 0 || wz >= g.nz) { if (g.pz) wz = wz < 0 ? wz + g.nz : wz - g.nz; else v = false; }
+            if (v) {
+                const uint32_t self = (uint32_t)wx + (uint32_t)g.nx * (uint32_t)wy + (uint32_t)g.nxy * (uint32_t)wz;
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                        (void *)(Am + (int64_t)a * g.plane), (short)0, (int)((uint32_t)g.n * sizeof(S)), kBufferFlags);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        r, (__attribute__((address_space(3))) void *)&pf.in[a][w][0], LdsBytes<S, PF>::value,
+                        (int)(pull_offset(g, a, self) * sizeof(S)), 0, 0, 0);
+                }
+            }
+        }
+    };
+
     // I(m) into LDS ring slots (index jm = m - z0 + 1) and the given registers
     auto first_step = [&](int m, int jm, T (&o0)[3], T (&op)[3], T (&om)[3]) {
         // The buffer descriptors of the 19 planes are rebuilt from the base
@@ -96,9 +136,16 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
         bool v = col;
         if (wz < 0 || wz >= g.nz) { if (g.pz) wz = wz < 0 ? wz + g.nz : wz - g.nz; else v = false; }
         T d[Q];
+        if constexpr (PF) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // this wave's prefetch has landed
         if (v) {
             const uint32_t self = (uint32_t)wx + (uint32_t)g.nx * (uint32_t)wy + (uint32_t)g.nxy * (uint32_t)wz;
-            gather<S, T, 0>(Am, g, p, wx, wy, wz, self, d);
+            if constexpr (PF) {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) d[a] = Conv<S, T>::load(pf.in[a][w][l]);
+                fix_edges<S, T>(Am, g, p, wx, wy, wz, self, d);
+            } else {
+                gather<S, T, 0>(Am, g, p, wx, wy, wz, self, d);
+            }
             collide<T, Forced, Route>(d, p, nullptr);
         } else {
 #pragma unroll
@@ -172,9 +219,18 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
     };
 
     // plane m = z0 - 1 .. z1: first step of I(m), then the output plane m - 1
+    prefetch(z0 - 1);
     for (int m = z0 - 1; m <= z1; ++m) {
         first_step(m, m - z0 + 1, r0n, rpn, rmn);
-        __syncthreads();
+        if (m < z1) prefetch(m + 1);
+        if constexpr (PF) {
+            // only the LDS ring writes must be visible to the other waves; the
+            // prefetch stays in flight across the barrier
+            __builtin_amdgcn_s_waitcnt(kWaitLgkmcnt0);
+            __builtin_amdgcn_s_barrier();
+        } else {
+            __syncthreads();
+        }
         if (m > z0) second_step(m - 1, m - z0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -186,7 +242,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
     }
 }
 
-template <typename S, typename T, bool Forced, int Route, int ROWS>
+template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF>
 static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T> &p, int planes, hipStream_t st) {
     FusedGrid L;
     L.gx = (uint32_t)((g.nx + kOut - 1) / kOut);
@@ -195,19 +251,19 @@ static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T
     L.gz = (uint32_t)((g.nz + planes - 1) / planes);
     const uint64_t nb = (uint64_t)L.gx * L.gy * L.gz;
     if (nb == 0 || nb > 0x7fffffffull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS>), dim3((uint32_t)nb), dim3(kLanes * ROWS),
+    hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF>), dim3((uint32_t)nb), dim3(kLanes * ROWS),
                        0, st, (const S *)A, (S *)B, g, p, L);
     return hipGetLastError();
 }
 
-template <typename S, typename T, int ROWS>
+template <typename S, typename T, int ROWS, bool PF = false>
 static hipError_t launch2_r(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
                             int planes, hipStream_t st) {
     if (route == 0)
-        return forced ? launch2_f<S, T, true, 0, ROWS>(A, B, g, p, planes, st)
-                      : launch2_f<S, T, false, 0, ROWS>(A, B, g, p, planes, st);
-    return forced ? launch2_f<S, T, true, 1, ROWS>(A, B, g, p, planes, st)
-                  : launch2_f<S, T, false, 1, ROWS>(A, B, g, p, planes, st);
+        return forced ? launch2_f<S, T, true, 0, ROWS, PF>(A, B, g, p, planes, st)
+                      : launch2_f<S, T, false, 0, ROWS, PF>(A, B, g, p, planes, st);
+    return forced ? launch2_f<S, T, true, 1, ROWS, PF>(A, B, g, p, planes, st)
+                  : launch2_f<S, T, false, 1, ROWS, PF>(A, B, g, p, planes, st);
 }
 
 hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
@@ -218,7 +274,9 @@ hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, cons
         if (rows != 8) return hipErrorInvalidValue;
         return launch2_r<double, double, 8>(A, B, g, pd, forced, route, planes, st);
     case 1:
+        // rows 12: the next plane's loads go straight to LDS (153 KiB in all)
         return rows == 16 ? launch2_r<float, float, 16>(A, B, g, pf, forced, route, planes, st)
+             : rows == 12 ? launch2_r<float, float, 12, true>(A, B, g, pf, forced, route, planes, st)
                           : launch2_r<float, float, 8>(A, B, g, pf, forced, route, planes, st);
     default:
         return rows == 16 ? launch2_r<__half, float, 16>(A, B, g, pf, forced, route, planes, st)

@@ -13,8 +13,9 @@ so its bound is looser and the FP64/FP32 cases carry the check.  The cases
 cover every wall kind (half-way bounce-back on each axis, the moving lid on
 +y, -x and +z, periodic axes), lattices narrower than one patch and spanning
 several patches along x, y and z, odd step counts (the remainder runs as one
-one-step launch), both patch heights, several z chunk lengths, the forced
-kernel and the printed-moment collision form.
+one-step launch), every patch height (12 rows: the FP32 variant whose loads go
+straight to LDS), several z chunk lengths, the forced kernel and the
+printed-moment collision form.
 """
 import numpy as np
 import pytest
@@ -71,7 +72,7 @@ def _compare(a, b, storage):
 
 
 @pytest.mark.parametrize("geom", list(_geometries()))
-@pytest.mark.parametrize("storage,rows", [("f64", 8), ("f32", 8), ("f32", 16), ("f16", 8), ("f16", 16)])
+@pytest.mark.parametrize("storage,rows", [("f64", 8), ("f32", 8), ("f32", 12), ("f32", 16), ("f16", 8), ("f16", 16)])
 def test_two_step_equals_one_step(clbm, geom, storage, rows):
     spec = _geometries()[geom]
     for steps, planes in ((7, 3), (4, 1), (6, max(1, spec.nz))):
@@ -100,7 +101,7 @@ def test_two_step_cavity_vs_oracle(clbm, storage, n):
     steps = 40
     f0 = W.perturbed_populations(spec, 5, 1e-3).numpy()
     _, u_ref = oracle.macroscopic(spec, oracle.run(spec, f0, steps))
-    rows = 8 if storage == "f64" else 16
+    rows = {"f64": 8, "f32": 12, "f16": 16}[storage]
     _, u = _run(clbm, spec, storage, steps, {"fuse_steps": 2, "fuse_rows": rows, "fuse_planes": 5}, seed=5, eps=1e-3)
     err = np.abs(u.cpu().numpy() - u_ref).max() / np.abs(u_ref).max()
     print(f"two-step cavity16 n={n} {storage}: {err:.3e}")
@@ -122,7 +123,8 @@ def test_two_step_poiseuille_vs_oracle(clbm):
 
 def test_launch_validation(clbm):
     lat = clbm.Lattice(W.cavity(8, 0.05, 1.0, 10.0), storage="f64")
-    for bad in ({"fuse_steps": 3}, {"fuse_steps": 2, "fuse_rows": 16}, {"fuse_planes": 0}, {"fuse_rows": 12}):
+    for bad in ({"fuse_steps": 3}, {"fuse_steps": 2, "fuse_rows": 16}, {"fuse_planes": 0}, {"fuse_rows": 12},
+                {"fuse_rows": 10}):
         with pytest.raises(clbm.ClbmError):
             lat.set_launch(**bad)
     lat.close()
