@@ -48,9 +48,9 @@ batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         T d[Q];
         gather<S, T, 0>(A + base, g, p, x, y, z, self, d);
         if (inst[i].forced)
-            collide<T, true, Route>(d, p, nullptr);
+            collide<T, true, Route, NewtonSteps<S>::value>(d, p, nullptr);
         else
-            collide<T, false, Route>(d, p, nullptr);
+            collide<T, false, Route, NewtonSteps<S>::value>(d, p, nullptr);
 #pragma unroll
         for (int a = 0; a < Q; ++a) Plane<S, 2>::store(B + base, g, a, self, d[a]);
     }

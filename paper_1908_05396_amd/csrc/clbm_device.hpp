@@ -178,7 +178,8 @@ __device__ inline T clampv(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
 // s is confined to [s_lo, s_hi] (one octave beyond log2 of the clip bounds of
 // tau - 1/2): if the root lies outside, the iterates stop at the window edge
 // and the final clamp of tau gives the clipped viscosity, as required.
-template <typename T>
+// NI: fixed Newton steps of the FP32 iteration (FP64 iterates to convergence).
+template <typename T, int NI = NewtonTol<T>::maxit>
 __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
     if (p.newtonian) return clampv(T(0.5) + p.three_K * fast_rcp(rho), p.tau_min, p.tau_max);
     const T q0 = a + b;
@@ -209,7 +210,7 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
     }
     const T two_k = T(2) * p.k;
     bool last = false;
-    for (int it = 0; it < NewtonTol<T>::maxit; ++it) {
+    for (int it = 0; it < (NewtonTol<T>::fixed ? NI : NewtonTol<T>::maxit); ++it) {
         const T e = fast_exp2(s);                 // tau - 1/2
         const T it1 = fast_rcp(T(0.5) + e);       // 1/tau
         const T q = a * (it1 * it1) + b;
@@ -282,7 +283,7 @@ __device__ inline void add_raw_moment_change(T d[Q], T dR0, T dRx, T dRy, T dRz,
 // the fourth-order ones to their attractors, so only moments up to second
 // order of the incoming state are needed.
 // ---------------------------------------------------------------------------
-template <typename T, bool Forced>
+template <typename T, bool Forced, int NI = NewtonTol<T>::maxit>
 __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out) {
     const T third = T(1) / T(3);
     // raw moments of the deviations (the rest part contributes 1, 0, 1/3, 0)
@@ -321,7 +322,7 @@ __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out
     const T m7 = cxx - cyy, m8 = cxx - czz, m9 = (cxx + cyy + czz) - D;
     const T a = T(3) * (m7 * m7 - m7 * m8 + m8 * m8) + T(9) * (kxy * kxy + kxz * kxz + kyz * kyz);
     const T b = T(1.5) * m9 * m9;   // omega_9 = 1
-    const T tau = solve_tau(p, rho, a, b);
+    const T tau = solve_tau<T, NI>(p, rho, a, b);
     const T om = fast_rcp(tau);
     if (omega_out) *omega_out = om;
     const T r = T(1) - om;
@@ -406,7 +407,7 @@ __device__ inline void collide_unit_high(T d[Q], const Relax<T> &p, T *omega_out
 // allowed.  With a body force the raw moments are those of the half-forced
 // state and the full source (central moments (0, F, 0, ...)) is added.
 // ---------------------------------------------------------------------------
-template <typename T, bool Forced>
+template <typename T, bool Forced, int NI = NewtonTol<T>::maxit>
 __device__ inline void collide_ghat(T d[Q], const Relax<T> &p, T *omega_out) {
     const T third = T(1) / T(3);
     // raw moments of the deviations (rest parts: 1, 1/3 on the diagonal, 1/9
@@ -464,7 +465,7 @@ __device__ inline void collide_ghat(T d[Q], const Relax<T> &p, T *omega_out) {
     const T m9 = (kxx + kyy + kzz) - (rho * (ux2 + uy2 + uz2) + D);
     const T a = T(3) * (m7 * m7 - m7 * m8 + m8 * m8) + T(9) * (m4 * m4 + m5 * m5 + m6 * m6);
     const T b = T(1.5) * p.omega_bulk * p.omega_bulk * m9 * m9;
-    const T om = fast_rcp(solve_tau(p, rho, a, b));
+    const T om = fast_rcp(solve_tau<T, NI>(p, rho, a, b));
     if (omega_out) *omega_out = om;
     const T w9 = p.omega_bulk;
     const T w10 = p.omega_high[0], w11 = p.omega_high[1], w12 = p.omega_high[2], w13 = p.omega_high[3];

@@ -146,7 +146,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
             } else {
                 gather<S, T, 0>(Am, g, p, wx, wy, wz, self, d);
             }
-            collide<T, Forced, Route>(d, p, nullptr);
+            collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
         } else {
 #pragma unroll
             for (int a = 0; a < Q; ++a) d[a] = T(0);
@@ -210,7 +210,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
                 d[a] = wall_value<T>(own, p, a, ghost_in_lid(g, sx, sy, sz));
             }
         }
-        collide<T, Forced, Route>(d, p, nullptr);
+        collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
         S *Bz = B;
         asm volatile("" : "+s"(Bz));
         const uint32_t self = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy + (uint32_t)g.nxy * (uint32_t)z;

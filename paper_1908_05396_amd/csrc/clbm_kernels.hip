@@ -33,7 +33,7 @@ stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<
     const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
     T d[Q];
     gather<S, T, LdAux>(A, g, p, x, y, z, self, d);
-    collide<T, Forced, Route>(d, p, nullptr);
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
 #pragma unroll
     for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B, g, a, self, d[a]);
 }
@@ -51,7 +51,7 @@ init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Re
     T d[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
-    collide<T, Forced, Route>(d, p, nullptr);
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
 #pragma unroll
     for (int a = 0; a < Q; ++a) Plane<S>::store(B, g, a, (uint32_t)i, d[a]);
 }

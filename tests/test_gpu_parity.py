@@ -267,3 +267,72 @@ def test_central_form_rejects_general_omegas(clbm):
     spec = W.cavity(8, 0.05, 1.0, 50.0).with_(**GENERAL_OMEGAS)
     with pytest.raises(clbm.ClbmError):
         clbm.Lattice(spec, storage="f32", collision="central")
+
+
+# ---------------------------------------------------------------------------
+# Square duct (Sec. 4.2): body force along the periodic axis, walls on two
+# axes.  Parity with the oracle for Newtonian and power-law fluids, and the
+# Newtonian steady state against the series solution printed in Sec. 4.2.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1.0, 0.7, 1.4])
+def test_duct_parity(clbm, storage, n):
+    """FP16-deviation storage is left out for the reason given for the
+    channel: F = 1e-6 per step is below the FP16 resolution of the stored
+    deviations (measured 4e-3 to 8e-3 normwise at 2000 steps)."""
+    # at 2000 steps the forced flow (F t = 2e-3) dominates the decayed start
+    # perturbation and |u| stays far above the FP64 rounding of the oracle's
+    # full populations (~1e-17 absolute per operation)
+    spec = W.duct(3, 45, n, 80.0)
+    steps = 2000
+    rho_ref, u_ref = _oracle_u(spec, 3, 1e-3, steps)
+    _, u, lat = _gpu_run(clbm, spec, storage, 3, 1e-3, steps)
+    lat.close()
+    err = _normwise(u, u_ref)
+    print(f"duct n={n} {storage}: {err:.3e} (max |u| {np.abs(u_ref).max():.2e})")
+    assert err < TOL_U[storage]
+
+
+def _series(H, F, nu, terms=80):
+    a = H / 2.0
+    c = np.arange(H) - (H - 1) / 2.0
+    Y, Z = np.meshgrid(c, c, indexing="ij")
+    u = np.zeros_like(Y)
+    for k in range(1, terms + 1):
+        m = 2 * k - 1
+        u += ((-1.0) ** (k - 1) * (1.0 - np.cosh(m * np.pi * Z / (2 * a)) / np.cosh(m * np.pi / 2))
+              * np.cos(m * np.pi * Y / (2 * a)) / m ** 3)
+    return 16.0 * a ** 2 * F / (nu * np.pi ** 3) * u
+
+
+@pytest.mark.parametrize("Re", [80.0, 20.0])
+def test_duct_steady_state_matches_series(clbm, Re):
+    """3 x 45 x 45 duct, F = 1e-6 (the paper's set-up), FP64, run until the
+    velocity changes by less than 1e-7 relative per 5000 steps (the residual
+    compares with an FP32 snapshot, whose rounding floor is ~3e-8).  Bound: the
+    oracle's second-order pin gives 4.8e-3 at H = 16 (Re 2); scaled by
+    (16/45)^2 that is 6e-4 at H = 45, and the bound allows a factor 5 for the
+    relaxation-rate dependence of the half-way wall position (omega 1.93 and
+    1.86 here against 1.79 there)."""
+    spec = W.duct(3, 45, 1.0, Re)
+    lat = clbm.Lattice(spec, storage="f64", track_residual=True)
+    lat.init_rest()
+    steps = 0
+    while steps < 600000:
+        lat.step(5000)
+        steps += 5000
+        r = lat.reduce()
+        if steps > 20000 and r["residual"] < 1e-7:
+            break
+    _, u = lat.macroscopic()
+    lat.close()
+    got = u[0].cpu().numpy()                       # (z, y, x)
+    ua = _series(45, spec.force[0], spec.K)        # [y, z]
+    prof = got[:, :, 1].T                          # [y, z]
+    assert np.abs(got[:, :, 0] - got[:, :, 2]).max() < 1e-14 * np.abs(got).max()   # uniform along x
+    err = np.sqrt(((prof - ua) ** 2).sum() / (ua ** 2).sum())
+    print(f"duct Re={Re}: {steps} steps, residual {r['residual']:.2e}, L2 error vs series {err:.3e}, "
+          f"u_max {prof.max():.4e} (series {ua.max():.4e})")
+    assert r["residual"] < 1e-7
+    assert err < 3e-3

@@ -414,3 +414,73 @@ def test_poiseuille_closed_form_second_order(n):
     assert e16 < 0.01
     order = np.log2(e8 / e16)
     assert 1.8 < order < 2.2
+
+
+# ---------------------------------------------------------------------------
+# Square duct (Sec. 4.2): Newtonian fully developed flow against the series
+# solution printed there, with second-order convergence.
+# ---------------------------------------------------------------------------
+
+def _duct_series(H, F, nu, terms=80):
+    """u(y, z) of the Newtonian square duct of half width a = H/2 (series of
+    Sec. 4.2, rho = 1) at the lattice nodes, indexed [y, z]."""
+    a = H / 2.0
+    c = np.arange(H) - (H - 1) / 2.0
+    Y, Z = np.meshgrid(c, c, indexing="ij")
+    u = np.zeros_like(Y)
+    for k in range(1, terms + 1):
+        m = 2 * k - 1
+        u += ((-1.0) ** (k - 1) * (1.0 - np.cosh(m * np.pi * Z / (2 * a)) / np.cosh(m * np.pi / 2))
+              * np.cos(m * np.pi * Y / (2 * a)) / m ** 3)
+    return 16.0 * a ** 2 * F / (nu * np.pi ** 3) * u
+
+
+def _duct_l2(H, Re=2.0, tol=1e-8, chunk=2000, maxsteps=200000):
+    # diffusive scaling: u_max = 0.08 / H at fixed Re, i.e. fixed nu = 0.04 / Re
+    umax = 0.08 / H
+    nu = umax * (H / 2.0) / Re
+    F = umax * nu / (W.duct_centre_coefficient() * (H / 2.0) ** 2)
+    spec = W.duct(1, H, 1.0, Re, F=F)
+    assert abs(spec.K - nu) < 1e-12 * nu
+    ua = _duct_series(H, F, nu)
+    u = np.zeros((3, H, H, 1))
+    u[0, :, :, 0] = ua.T                      # (z, y) layout of the lattice
+    f = _eq_linear(u)
+    prev, steps = None, 0
+    while steps < maxsteps:
+        f = oracle.run(spec, f, chunk)
+        steps += chunk
+        _, uu = oracle.macroscopic(spec, f)
+        if prev is not None and np.abs(uu[0] - prev).max() / umax < tol:
+            break
+        prev = uu[0].copy()
+    got = uu[0, :, :, 0].T                    # [y, z]
+    return np.sqrt(((got - ua) ** 2).sum() / (ua ** 2).sum()), got
+
+
+def test_duct_series_newtonian_second_order():
+    """The steady oracle duct flow approaches the series solution of Sec. 4.2
+    with order 2, and is symmetric under y <-> z (walls on both axes)."""
+    e8, _ = _duct_l2(8)
+    e16, u16 = _duct_l2(16)
+    assert np.abs(u16 - u16.T).max() < 1e-10 * np.abs(u16).max()
+    assert e16 < 0.01
+    order = np.log2(e8 / e16)
+    assert 1.8 < order < 2.2, (e8, e16, order)
+
+
+def test_duct_series_is_the_poisson_solution():
+    """The series itself: zero on the walls and -lap(u) = F/nu inside
+    (finite differences on a fine grid), so a transcription slip in the
+    series would not let the oracle check above pass by accident."""
+    H, F, nu = 400, 1e-6, 0.01
+    a = H / 2.0
+    u = _duct_series(H, F, nu, terms=200)
+    h = 1.0
+    lap = (u[2:, 1:-1] + u[:-2, 1:-1] + u[1:-1, 2:] + u[1:-1, :-2] - 4 * u[1:-1, 1:-1]) / h ** 2
+    inner = lap[20:-20, 20:-20]
+    assert np.abs(-inner * nu / F - 1).max() < 1e-3
+    # extrapolated to the wall (half a node beyond the outer nodes) the profile vanishes
+    edge = 1.5 * u[0, :] - 0.5 * u[1, :]
+    assert np.abs(edge).max() < 2e-3 * u.max()
+    assert abs(u[H // 2, H // 2] / (F * a ** 2 / nu) - W.duct_centre_coefficient()) < 1e-4

@@ -97,6 +97,27 @@ def poiseuille(nx: int, ny: int, nz: int, n: float, Re: float, umax: float, name
                        name=name or f"poiseuille{nx}x{ny}x{nz}")
 
 
+def duct_centre_coefficient(terms: int = 60) -> float:
+    """C in u_max = C F a^2 / nu for the Newtonian square duct of half width a:
+    the centre value (y = z = 0) of the series solution quoted in Sec. 4.2,
+    C = 16/pi^3 sum_k (-1)^(k-1) [1 - 1/cosh((2k-1) pi/2)] / (2k-1)^3."""
+    k = np.arange(1, terms + 1)
+    m = 2 * k - 1
+    return float(16.0 / np.pi ** 3 * np.sum((-1.0) ** (k - 1) * (1.0 - 1.0 / np.cosh(m * np.pi / 2)) / m ** 3))
+
+
+def duct(nx: int, H: int, n: float, Re: float, F: float = 1e-6, name="") -> LatticeSpec:
+    """Square duct (Sec. 4.2): walls normal to y and z, H fluid nodes across
+    (half width a = H/2 with half-way walls), periodic along x, body force F
+    along x.  Re = u_max a / nu with the Newtonian centre velocity
+    u_max = C F a^2 / nu, so nu = sqrt(C F a^3 / Re); that nu is used as the
+    consistency K for every n (rho = 1)."""
+    a = H / 2.0
+    K = float(np.sqrt(duct_centre_coefficient() * F * a ** 3 / Re))
+    return LatticeSpec(nx=nx, ny=H, nz=H, K=K, n=n, periodic=(1, 0, 0), force=(F, 0.0, 0.0),
+                       name=name or f"duct{nx}x{H}x{H}_n{n}_re{Re:g}")
+
+
 # ---------------------------------------------------------------------------
 # The five benchmark workloads
 # ---------------------------------------------------------------------------
