@@ -213,6 +213,42 @@ def accuracy_run(clbm, torch, spec, steps, report_every):
     return out
 
 
+def stability(clbm, torch, W, steps=50000, check_every=5000):
+    """Largest stable lid velocity of the 64^3 cavity (the protocol of Sec. 5:
+    mu_p = c_s^2 (tau_p - 1/2), stable = finite with max |u| below 1 after
+    `steps` steps) for the cascaded scheme and the BGK comparison model, by
+    bisection on U.  The viscosity clip is opened to omega < 2 - 1e-6, as the
+    protocol has none."""
+    nu_min = (1.0 / (2.0 - 1e-6) - 0.5) / 3.0
+    out = []
+    for n in (0.8, 1.0, 1.5):
+        for tau_p in (0.51, 0.55, 0.6):
+            row = {"n": n, "tau_p": tau_p}
+            for model in ("cascaded", "srt"):
+                lo, hi = 0.0, 0.4
+                for _ in range(7):
+                    U = 0.5 * (lo + hi)
+                    spec = W.LatticeSpec(nx=64, ny=64, nz=64, K=(tau_p - 0.5) / 3.0, n=n, lid_face=W.LID_PY,
+                                         lid_velocity=(U, 0.0, 0.0), nu_min=nu_min, model=model)
+                    lat = clbm.Lattice(spec, storage="f32", track_residual=False)
+                    lat.init_rest()
+                    ok, done = True, 0
+                    while done < steps:
+                        lat.step(check_every)
+                        done += check_every
+                        r = lat.reduce(raise_unstable=False)
+                        if r["nonfinite"] > 0 or not (r["umax"] < 1.0):
+                            ok = False
+                            break
+                    lat.close()
+                    lo, hi = (U, hi) if ok else (lo, U)
+                row[model + "_max_U"] = round(lo, 4)
+                print(f"[stability] n={n} tau_p={tau_p} {model}: max stable U in [{lo:.4f}, {hi:.4f})",
+                      file=sys.stderr, flush=True)
+            out.append(row)
+    return {"workload": "cavity64, FP32, 50000 steps, bisection on U in (0, 0.4)", "rows": out}
+
+
 def copy_bandwidth(clbm, torch, nbytes=4 << 30, reps=10):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
@@ -272,6 +308,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--stability", action="store_true",
+                    help="instead of the benchmark: largest stable lid velocity of the 64^3 cavity, cascaded "
+                         "scheme vs the single-relaxation-time comparison model")
     ap.add_argument("--accuracy256", type=int, default=0, metavar="STEPS",
                     help="instead of the benchmark: run the 256^3 cavity (Re 1000, n 0.5) for STEPS steps in "
                          "FP64, FP32 and FP16-deviation storage and print the centreline errors vs FP64")
@@ -290,6 +329,9 @@ def main():
     from paper_1908_05396_amd import clbm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.stability:
+        print(json.dumps(stability(clbm, torch, W)), flush=True)
+        return
     if args.accuracy256:
         print(json.dumps(accuracy_run(clbm, torch, W.config_cavity256(), args.accuracy256, 5000)), flush=True)
         return
@@ -331,6 +373,16 @@ def main():
                 "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
                                        / HBM_PEAK_GBS, 4)}
 
+    # the single-relaxation-time comparison model on the same workload (FP32)
+    comparison = None
+    if not args.no_variants:
+        r = time_lattice(clbm, torch, spec.with_(model="srt"), "f32", 300, 20, args.reduce_every)
+        comparison = {"model": "single-relaxation-time (BGK), same power law, FP32, 300 steps",
+                      "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+                      "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
+                      "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3)
+                                             / 1e9 / HBM_PEAK_GBS, 4)}
+
     accuracy = None
     if compare:
         accuracy = accuracy_vs(torch, fields, "f64", spec.lid_velocity[0], args.size)
@@ -360,6 +412,7 @@ def main():
         "mass_drift": main_run["mass_drift"],
         "variants": variants,
         "other_launch_form": launch_forms,
+        "srt_comparison": comparison,
         "accuracy": accuracy,
     }
     if not args.no_batch:

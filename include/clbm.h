@@ -75,7 +75,10 @@ typedef enum {
 typedef enum {
     CLBM_COLLIDE_AUTO = 0,     /* central-moment form when omega_9..18 are all 1, else printed form */
     CLBM_COLLIDE_CENTRAL = 1,  /* requires omega_9..18 = 1 */
-    CLBM_COLLIDE_GHAT = 2
+    CLBM_COLLIDE_GHAT = 2,
+    CLBM_COLLIDE_SRT = 3       /* not the paper's scheme: its single-relaxation-time (BGK) comparison
+                                  model (Sec. 5) with the same power-law relaxation time, for cost and
+                                  stability comparisons; unforced, one step per launch, no batches */
 } clbm_collision;
 
 typedef enum {

@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("force", ctypes.c_double * 3),
         ("lid_velocity", ctypes.c_double * 3),
         ("rho_wall", ctypes.c_double),
+        ("model", ctypes.c_int32),
     ]
 
 
@@ -97,6 +98,10 @@ def _params(spec) -> _Params:
     for k in range(9):
         p.omega_high[k] = float(spec.omega_high[k])
     p.rho_wall = float(spec.rho_wall)
+    model = getattr(spec, "model", "cascaded")
+    if model not in ("cascaded", "srt"):
+        raise ValueError(f"unknown model {model!r}")
+    p.model = 1 if model == "srt" else 0
     return p
 
 

@@ -40,6 +40,9 @@
  *      periodic axes, half-way bounce-back walls and a moving-lid momentum
  *      correction (Sec. 4.1, 4.2, 4.3).
  *
+ * model = 1 selects instead the single-relaxation-time (BGK) comparison model
+ * of Sec. 5 with the same power-law relaxation time (see collide_node_srt).
+ *
  * Conventions: lattice units, c_s^2 = 1/3, node index x + nx*(y + ny*z),
  * populations stored as structure of arrays f[alpha*N + node].
  * No fast-math: every operation is IEEE double with round-to-nearest.
@@ -68,6 +71,7 @@ typedef struct {
     double force[3];       /* body force per unit volume */
     double lid_velocity[3];
     double rho_wall;       /* density in the moving-wall correction */
+    int32_t model;         /* 0: the cascaded scheme; 1: single-relaxation-time BGK (comparison model) */
 } orc_params;
 
 /* D3Q19 particle velocities, alpha = 0..18, read off the component vectors
@@ -262,11 +266,72 @@ static double solve_omega_nu(const orc_params *p, double rho, const double m[10]
 }
 
 /* ---------------------------------------------------------------------- */
+/* Single-relaxation-time comparison model (Sec. 5)                         */
+/* ---------------------------------------------------------------------- */
+/* The paper compares its scheme with the SRT (BGK) model, in which every
+ * population relaxes at the one rate 1/tau, tau set locally by the same
+ * power-law equation; it does not print that model.  Textbook form used
+ * here (Qian, d'Humieres & Lallemand 1992; Kruger et al. 2017, Ch. 3, 4, 10):
+ *   f_eq = w rho (1 + e.u/cs2 + (e.u)^2/(2 cs2^2) - u.u/(2 cs2)),
+ *   Pi_neq = sum e e (f - f_eq),  S = -Pi_neq / (2 rho cs2 tau),
+ *   f~ = f - (f - f_eq) / tau.  Unforced. */
+static double shear_rate_srt(double tau, double rho, const double pi[6]) {
+    double c = -1.0 / (2.0 * rho * CS2 * tau);
+    double sxx = c * pi[0], syy = c * pi[1], szz = c * pi[2];
+    double sxy = c * pi[3], sxz = c * pi[4], syz = c * pi[5];
+    return sqrt(2.0 * (sxx * sxx + syy * syy + szz * szz + 2.0 * (sxy * sxy + sxz * sxz + syz * syz)));
+}
+
+static double srt_residual(const orc_params *p, double tau, double rho, const double pi[6]) {
+    return tau - 0.5 - clipped_nu(p, shear_rate_srt(tau, rho, pi), rho) / CS2;
+}
+
+/* The same bisection on tau over the clip interval as for the cascaded rate. */
+static double solve_tau_srt(const orc_params *p, double rho, const double pi[6]) {
+    double lo = p->nu_min / CS2 + 0.5, hi = p->nu_max / CS2 + 0.5;
+    double hlo = srt_residual(p, lo, rho, pi), hhi = srt_residual(p, hi, rho, pi);
+    if (hlo != hlo || hhi != hhi) return NAN;
+    if (hlo >= 0.0) return lo;
+    if (hhi <= 0.0) return hi;
+    for (int it = 0; it < 2000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        double h = srt_residual(p, mid, rho, pi);
+        if (h > 0.0) { hi = mid; hhi = h; }
+        else { lo = mid; hlo = h; }
+    }
+    return (fabs(hlo) <= fabs(hhi)) ? lo : hi;
+}
+
+static int collide_node_srt(const orc_params *p, const double *f, double *fout, double *omega_out) {
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < Q; ++a) {
+        rho += f[a];
+        j[0] += EX[a] * f[a]; j[1] += EY[a] * f[a]; j[2] += EZ[a] * f[a];
+    }
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double feq[Q], pi[6] = {0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < Q; ++a) {
+        double eu = EX[a] * u[0] + EY[a] * u[1] + EZ[a] * u[2];
+        feq[a] = W[a] * rho * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+        double ne = f[a] - feq[a];
+        pi[0] += EX[a] * EX[a] * ne; pi[1] += EY[a] * EY[a] * ne; pi[2] += EZ[a] * EZ[a] * ne;
+        pi[3] += EX[a] * EY[a] * ne; pi[4] += EX[a] * EZ[a] * ne; pi[5] += EY[a] * EZ[a] * ne;
+    }
+    double tau = solve_tau_srt(p, rho, pi);
+    for (int a = 0; a < Q; ++a) fout[a] = f[a] - (f[a] - feq[a]) / tau;
+    if (omega_out) *omega_out = 1.0 / tau;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Collision of one node                                                    */
 /* ---------------------------------------------------------------------- */
 
 int orc_collide_node(const orc_params *p, const double *fin, double *fout, double *omega_out) {
     init_tables();
+    if (p->model == 1) return collide_node_srt(p, fin, fout, omega_out);
     double f[Q];
     memcpy(f, fin, sizeof(f));
     const double *F = p->force;
@@ -380,6 +445,8 @@ static int valid_params(const orc_params *p) {
     if (!(p->K > 0.0) || !(p->n > 0.0)) return 0;
     if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min)) return 0;
     if (p->lid_face < 0 || p->lid_face > 6) return 0;
+    if (p->model != 0 && p->model != 1) return 0;
+    if (p->model == 1 && (p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0)) return 0;
     return 1;
 }
 

@@ -16,7 +16,7 @@ LIBPATH = os.path.join(_HERE, "libclbm.so")
 
 Q = 19
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
-COLLISION = {"auto": 0, "central": 1, "ghat": 2}
+COLLISION = {"auto": 0, "central": 1, "ghat": 2, "srt": 3}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
 
 CLBM_OK, CLBM_EINVAL, CLBM_ENOMEM, CLBM_EHIP, CLBM_EUNSTABLE, CLBM_ESTATE = 0, -1, -2, -3, -4, -5
@@ -164,6 +164,8 @@ def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, pl
     p.attractor_literal = int(getattr(spec, "attractor_literal", 0))
     p.track_residual = 1 if track_residual else 0
     p.plane_pad = int(plane_pad)
+    if getattr(spec, "model", "cascaded") == "srt":
+        collision = "srt"
     p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     p.K, p.n = float(spec.K), float(spec.n)
     p.nu_min, p.nu_max = float(spec.nu_min), float(spec.nu_max)

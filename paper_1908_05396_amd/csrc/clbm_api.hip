@@ -269,6 +269,8 @@ clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
                          (c->fuse_rows == 12 && h->prm.storage == CLBM_F32);
     if (!rows_ok) return fail(CLBM_EINVAL, "fuse_rows must be 8, 16 (not FP64) or 12 (FP32 only)");
     if (c->fuse_planes < 1) return fail(CLBM_EINVAL, "fuse_planes must be >= 1");
+    if (c->fuse_steps == 2 && h->route == 2)
+        return fail(CLBM_EINVAL, "the single-relaxation-time model runs one step per launch");
     if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
     h->launch.bx = c->bx;
     h->launch.by = c->by;

@@ -289,6 +289,8 @@ clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *byte
         clbm_status st = validate(&inst[i]);
         if (st != CLBM_OK) return fail(st, "instance %d: %s", i, g_err.c_str());
         if (inst[i].storage != inst[0].storage) return fail(CLBM_EINVAL, "instance %d: storage differs", i);
+        if (inst[i].collision == CLBM_COLLIDE_SRT)
+            return fail(CLBM_EINVAL, "instance %d: batches run the cascaded scheme only", i);
         // the row of a node within its layer comes from a float estimate with
         // one correction, exact while a layer has at most 2^22 nodes
         if ((int64_t)inst[i].nx * inst[i].ny > ((int64_t)1 << 22))

@@ -590,6 +590,49 @@ __device__ inline void collide_ghat(T d[Q], const Relax<T> &p, T *omega_out) {
 }
 
 // ---------------------------------------------------------------------------
+// Single-relaxation-time (BGK) collision with the power-law relaxation time:
+// the comparison model of Sec. 5, where every population relaxes at the one
+// rate 1/tau towards the second-order polynomial equilibrium (textbook D3Q19
+// form).  The strain rate of this model is S = -Pi_neq / (2 rho c_s^2 tau), so
+// |gamma|^2 = 4.5 Pi_neq:Pi_neq / (rho tau)^2 and tau solves the same local
+// equation as the cascaded rate with a = 4.5 Pi_neq:Pi_neq and b = 0.  On
+// deviations d = f - w: f_eq - w = w (D + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u))
+// and Pi_neq = M(d) - J u - D/3 I, with M(d) the second moments of d.
+// Unforced only.
+// ---------------------------------------------------------------------------
+template <typename T, int NI = NewtonTol<T>::maxit>
+__device__ inline void collide_srt(T d[Q], const Relax<T> &p, T *omega_out) {
+    const T third = T(1) / T(3);
+    const T exy_p = d[7] + d[10], exy_m = d[8] + d[9];
+    const T exz_p = d[11] + d[14], exz_m = d[12] + d[13];
+    const T eyz_p = d[15] + d[18], eyz_m = d[16] + d[17];
+    const T Exy = exy_p + exy_m, Exz = exz_p + exz_m, Eyz = eyz_p + eyz_m;
+    const T Fx = d[1] + d[2], Fy = d[3] + d[4], Fz = d[5] + d[6];
+    const T D = d[0] + (Fx + Fy + Fz) + (Exy + Exz + Eyz);          // rho - 1
+    const T Jx = (d[1] - d[2]) + ((d[7] - d[10]) + (d[9] - d[8])) + ((d[11] - d[14]) + (d[13] - d[12]));
+    const T Jy = (d[3] - d[4]) + ((d[7] - d[10]) + (d[8] - d[9])) + ((d[15] - d[18]) + (d[17] - d[16]));
+    const T Jz = (d[5] - d[6]) + ((d[11] - d[14]) + (d[12] - d[13])) + ((d[15] - d[18]) + (d[16] - d[17]));
+    const T Mxy = exy_p - exy_m, Mxz = exz_p - exz_m, Myz = eyz_p - eyz_m;
+    const T Mxx = Fx + Exy + Exz, Myy = Fy + Exy + Eyz, Mzz = Fz + Exz + Eyz;
+    const T rho = T(1) + D;
+    const T irho = fast_rcp(rho);
+    const T ux = Jx * irho, uy = Jy * irho, uz = Jz * irho;
+    const T d3 = D * third;
+    const T pxx = Mxx - Jx * ux - d3, pyy = Myy - Jy * uy - d3, pzz = Mzz - Jz * uz - d3;
+    const T pxy = Mxy - Jx * uy, pxz = Mxz - Jx * uz, pyz = Myz - Jy * uz;
+    const T a = T(4.5) * ((pxx * pxx + pyy * pyy + pzz * pzz) + T(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+    const T om = fast_rcp(solve_tau<T, NI>(p, rho, a, T(0)));
+    if (omega_out) *omega_out = om;
+    const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const T eu = T(cx(q)) * ux + T(cy(q)) * uy + T(cz(q)) * uz;
+        const T deq = (T)weight(q) * (D + rho * (T(3) * eu + T(4.5) * eu * eu - usq));
+        d[q] += om * (deq - d[q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Wall rules.  A ghost (source outside the lattice on a non-periodic axis)
 // lies in the lid plane when its coordinate along the lid axis is just beyond
 // the lid face; edges and corners of that plane included.

@@ -268,7 +268,7 @@ static hipError_t launch2_r(const void *A, void *B, const Geom &g, const Relax<T
 
 hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                         const Relax<float> &pf, bool forced, int route, int rows, int planes, hipStream_t st) {
-    if (planes < 1) return hipErrorInvalidValue;
+    if (planes < 1 || route == 2) return hipErrorInvalidValue;   // no two-step form of the BGK model
     switch (storage) {
     case 0:
         if (rows != 8) return hipErrorInvalidValue;

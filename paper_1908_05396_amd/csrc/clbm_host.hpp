@@ -62,6 +62,7 @@ inline bool unit_high_omegas(const clbm_params *p) {
 }
 
 inline int route_of(const clbm_params *p) {
+    if (p->collision == CLBM_COLLIDE_SRT) return 2;
     if (p->collision == CLBM_COLLIDE_GHAT) return 1;
     if (p->collision == CLBM_COLLIDE_CENTRAL) return 0;
     return unit_high_omegas(p) ? 0 : 1;
@@ -86,8 +87,10 @@ inline clbm_status validate(const clbm_params *p) {
     for (int k = 0; k < 9; ++k)
         if (!(p->omega_high[k] > 0.0 && p->omega_high[k] < 2.0))
             return fail(CLBM_EINVAL, "omega_high[%d] must lie in (0, 2)", k);
-    if (p->collision < CLBM_COLLIDE_AUTO || p->collision > CLBM_COLLIDE_GHAT)
+    if (p->collision < CLBM_COLLIDE_AUTO || p->collision > CLBM_COLLIDE_SRT)
         return fail(CLBM_EINVAL, "unknown collision form %d", p->collision);
+    if (p->collision == CLBM_COLLIDE_SRT && (p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0))
+        return fail(CLBM_EINVAL, "the single-relaxation-time model is unforced");
     if (p->collision == CLBM_COLLIDE_CENTRAL && !unit_high_omegas(p))
         return fail(CLBM_EINVAL, "the central-moment form needs omega_bulk = omega_high = 1");
     for (int d = 0; d < 3; ++d) {

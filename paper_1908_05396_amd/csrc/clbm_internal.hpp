@@ -41,12 +41,17 @@ hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, co
 
 // Collision forms: 0 = central-moment form for omega_9..18 = 1, 1 = the
 // paper's printed changes of moments g4..g18 with f~ = f + K.g.
+// Route 2: the single-relaxation-time comparison model (unforced only).
 template <typename T, bool Forced, int Route, int NI = NewtonTol<T>::maxit>
 __device__ inline void collide(T d[Q], const Relax<T> &p, T *omega_out) {
-    if constexpr (Route == 0)
+    if constexpr (Route == 0) {
         collide_unit_high<T, Forced, NI>(d, p, omega_out);
-    else
+    } else if constexpr (Route == 1) {
         collide_ghat<T, Forced, NI>(d, p, omega_out);
+    } else {
+        static_assert(!Forced, "the single-relaxation-time model is unforced");
+        collide_srt<T, NI>(d, p, omega_out);
+    }
 }
 
 // Newton steps of the FP32 relaxation-rate solve per storage type: four reach

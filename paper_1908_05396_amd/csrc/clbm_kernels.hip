@@ -241,6 +241,7 @@ static hipError_t launch_step_f(const void *A, void *B, const Geom &g, const Rel
 template <typename S, typename T>
 static hipError_t launch_step_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
                                 const StepLaunch &c, hipStream_t st) {
+    if (route == 2) return forced ? hipErrorInvalidValue : launch_step_f<S, T, false, 2>(A, B, g, p, c, st);
     if (route == 0)
         return forced ? launch_step_f<S, T, true, 0>(A, B, g, p, c, st) : launch_step_f<S, T, false, 0>(A, B, g, p, c, st);
     return forced ? launch_step_f<S, T, true, 1>(A, B, g, p, c, st) : launch_step_f<S, T, false, 1>(A, B, g, p, c, st);
@@ -260,7 +261,10 @@ static hipError_t launch_init_t(const double *f0, void *B, const Geom &g, const 
                                 hipStream_t st) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     dim3 grid((unsigned)((N + 255) / 256)), block(256);
-    if (route == 0) {
+    if (route == 2) {
+        if (forced) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((init_collide_kernel<S, T, false, 2>), grid, block, 0, st, f0, (S *)B, g, p);
+    } else if (route == 0) {
         if (forced)
             hipLaunchKernelGGL((init_collide_kernel<S, T, true, 0>), grid, block, 0, st, f0, (S *)B, g, p);
         else

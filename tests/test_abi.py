@@ -78,7 +78,7 @@ def test_buffer_size_padding(clbm, storage, esize):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("K", 0.0), ("K", float("nan")), ("n", -1.0), ("nu_min", 0.0), ("nu_max", 1e-6),
     ("omega_bulk", 2.0), ("rho_wall", 0.0), ("storage", 7), ("lid_face", 9), ("attractor_literal", 2),
-    ("collision", 3), ("plane_pad", -2),
+    ("collision", 4), ("plane_pad", -2),
 ])
 def test_invalid_parameters_rejected(clbm, field, value):
     p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")
@@ -123,3 +123,19 @@ def test_batch_size_validates_each_instance(clbm):
     arr[1].K = -1.0
     assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
     assert clbm.load().clbm_batch_size(arr, 0, ctypes.byref(n)) == clbm.CLBM_EINVAL
+
+
+def test_srt_model_restrictions(clbm):
+    """The single-relaxation-time comparison model is unforced and is not
+    offered in batches."""
+    spec = W.poiseuille(4, 8, 4, n=1.0, Re=5.0, umax=0.01).with_(model="srt")
+    with pytest.raises(clbm.ClbmError):
+        clbm.buffer_size(clbm.params_from_spec(spec, "f32"))
+    cav = W.cavity(8, 0.05, 1.0, 10.0).with_(model="srt")
+    p = clbm.params_from_spec(cav, "f32")
+    assert p.collision == clbm.COLLISION["srt"]
+    clbm.buffer_size(p)
+    arr = (clbm.Params * 1)()
+    arr[0] = p
+    n = ctypes.c_size_t()
+    assert clbm.load().clbm_batch_size(arr, 1, ctypes.byref(n)) == clbm.CLBM_EINVAL

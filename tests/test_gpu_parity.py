@@ -336,3 +336,44 @@ def test_duct_steady_state_matches_series(clbm, Re):
           f"u_max {prof.max():.4e} (series {ua.max():.4e})")
     assert r["residual"] < 1e-7
     assert err < 3e-3
+
+
+# ---------------------------------------------------------------------------
+# The single-relaxation-time comparison model (Sec. 5), same power law
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage,tol", [("f64", 5e-15), ("f32", 1e-6), ("f16", 2e-5)])
+def test_srt_single_collision_populations(clbm, storage, tol):
+    """One BGK collision of a strongly perturbed state, element by element
+    (bounds as for the cascaded collision)."""
+    spec = W.cavity(16, 0.05, 0.6, 100.0).with_(nx=13, ny=11, nz=9, model="srt", name="srt13x11x9")
+    f0 = W.perturbed_populations(spec, 7, 2e-2)
+    lat = clbm.Lattice(spec, storage=storage)
+    lat.init_populations(f0.to("cuda"))
+    f_gpu = lat.populations().cpu().numpy()
+    lat.close()
+    f_ref = oracle.collide(spec, f0.numpy())
+    err = np.abs(f_gpu - f_ref).max()
+    print(f"srt collide {storage}: max abs diff {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("n", [0.5, 1.0, 1.5])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_srt_cavity16(clbm, n, storage):
+    """16^3 cavity with the BGK model, perturbed start, 300 steps; FP16 on the
+    centrelines as for the cascaded cavity."""
+    spec = W.cavity(16, 0.05, n, 100.0, name=f"srt_cavity16_n{n}").with_(model="srt")
+    rho_ref, u_ref = _oracle_u(spec, 1234, 1e-3, 300)
+    rho, u, lat = _gpu_run(clbm, spec, storage, 1234, 1e-3, 300)
+    lat.close()
+    err = _normwise(u, u_ref)
+    print(f"srt cavity16 n={n} {storage}: {err:.3e}")
+    if storage != "f16":
+        assert err < TOL_U[storage]
+        return
+    c = 8
+    cl = max(np.abs(u[0, c, :, c] - u_ref[0, c, :, c]).max(),
+             np.abs(u[1, c, c, :] - u_ref[1, c, c, :]).max()) / np.abs(u_ref).max()
+    assert cl < TOL_U["f16"]
+    assert err < 2e-2

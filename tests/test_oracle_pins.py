@@ -328,11 +328,11 @@ def test_cavity_mass_and_mirror_symmetry():
 # Flows with closed-form solutions
 # ---------------------------------------------------------------------------
 
-def _couette(n, U, H=8, steps=8000):
+def _couette(n, U, H=8, steps=8000, model="cascaded"):
     g = U / H
     K = 0.1 / g ** (n - 1)
     spec = W.LatticeSpec(nx=1, ny=H, nz=1, K=K, n=n, periodic=(1, 0, 1), lid_face=W.LID_PY,
-                         lid_velocity=(U, 0.0, 0.0))
+                         lid_velocity=(U, 0.0, 0.0), model=model)
     y = np.arange(H)
     u = np.zeros((3, 1, H, 1))
     u[0, 0, :, 0] = U * (y + 0.5) / H
@@ -344,27 +344,29 @@ def _couette(n, U, H=8, steps=8000):
     return uerr, np.abs(om - om_exact).max() / om_exact
 
 
+@pytest.mark.parametrize("model", ["cascaded", "srt"])
 @pytest.mark.parametrize("n", [0.5, 1.5])
-def test_power_law_couette(n):
+def test_power_law_couette(n, model):
     """Plate moving at U over H nodes (Eqs. 5-6): the exact steady solution is
     linear with uniform |gamma| = U/H, hence uniform omega^nu =
     1/(3 K (U/H)^(n-1) + 1/2).  This pins the strain-rate estimate, the
     power-law viscosity and the moving-wall term.  The weakly compressible
     scheme leaves an O(U^2) (Mach-squared) remainder: it must shrink by 4 when
     U halves, and stay below 0.05 U^2 (velocity) and 0.1 U^2 (omega)."""
-    e1u, e1o = _couette(n, 0.02)
-    e2u, e2o = _couette(n, 0.01)
+    e1u, e1o = _couette(n, 0.02, model=model)
+    e2u, e2o = _couette(n, 0.01, model=model)
     assert e1u < 0.05 * 0.02 ** 2 and e1o < 0.1 * 0.02 ** 2
     assert e2u < 0.05 * 0.01 ** 2 and e2o < 0.1 * 0.01 ** 2
     assert 3.5 < e1u / e2u < 4.5 and 3.5 < e1o / e2o < 4.5
 
 
-def test_shear_wave_decay_gives_newtonian_viscosity():
+@pytest.mark.parametrize("model", ["cascaded", "srt"])
+def test_shear_wave_decay_gives_newtonian_viscosity(model):
     """n = 1: a transverse shear wave decays as exp(-nu k^2 t) with
     nu = c_s^2 (1/omega - 1/2) (Sec. 3.1).  A 64-node period keeps the
     lattice correction to the decay rate well under 1e-3."""
     L, U0, K = 64, 1e-3, 0.05
-    spec = W.LatticeSpec(nx=1, ny=L, nz=1, K=K, n=1.0, periodic=(1, 1, 1))
+    spec = W.LatticeSpec(nx=1, ny=L, nz=1, K=K, n=1.0, periodic=(1, 1, 1), model=model)
     k = 2 * np.pi / L
     y = np.arange(L)
     u = np.zeros((3, 1, L, 1))
@@ -484,3 +486,41 @@ def test_duct_series_is_the_poisson_solution():
     edge = 1.5 * u[0, :] - 0.5 * u[1, :]
     assert np.abs(edge).max() < 2e-3 * u.max()
     assert abs(u[H // 2, H // 2] / (F * a ** 2 / nu) - W.duct_centre_coefficient()) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# The single-relaxation-time comparison model (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def test_srt_conserves_mass_and_momentum_and_rest():
+    rng = np.random.default_rng(11)
+    E = _E()
+    for n in (0.5, 1.0, 1.5):
+        spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=0.02, n=n, model="srt")
+        for _ in range(10):
+            f = _random_state(rng)
+            ft, _ = oracle.collide_node(spec, f)
+            # rounding of 19 full populations (~0.05-0.33) bounds the drift
+            assert abs(ft.sum() - f.sum()) <= 2e-15 * f.sum()
+            assert np.allclose(E.T @ ft, E.T @ f, rtol=0, atol=1e-15)
+        w = oracle.weights()
+        ft, _ = oracle.collide_node(spec, w)
+        assert np.abs(ft - w).max() <= 6e-16
+
+
+def test_srt_relaxes_to_the_second_order_equilibrium():
+    """At tau = 1 (n = 1, K = 1/6, rho = 1) one BGK collision lands on the
+    equilibrium, whose defining moments are rho, rho u and
+    rho c_s^2 I + rho u u (Sec. 3 lists the same for the continuous
+    Maxwellian)."""
+    rng = np.random.default_rng(5)
+    E = _E()
+    spec = W.LatticeSpec(nx=1, ny=1, nz=1, K=1.0 / 6.0, n=1.0, model="srt")
+    for _ in range(10):
+        f = _random_state(rng)
+        f = f / f.sum()
+        ft, om = oracle.collide_node(spec, f)
+        assert abs(om - 1.0) < 1e-15
+        j = E.T @ f
+        second = np.einsum("a,ai,aj->ij", ft, E, E)
+        assert np.allclose(second, np.eye(3) / 3.0 + np.outer(j, j), rtol=0, atol=2e-15)

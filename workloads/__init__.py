@@ -51,6 +51,7 @@ class LatticeSpec:
     omega_high: Tuple[float, ...] = (1.0,) * 9
     rho_wall: float = 1.0
     attractor_literal: int = 0     # 1: fourth-order attractors without the 1/rho factor
+    model: str = "cascaded"        # "cascaded" (the paper's scheme) or "srt" (its BGK comparison model)
     name: str = ""
 
     @property
