@@ -137,6 +137,20 @@ clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane_stride, size_t
 clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each,
                         clbm_lattice **out);
 
+/* Create a lattice over ONE caller-owned state buffer (half the memory of
+ * clbm_create), stepped in place with the AA access pattern: an even step
+ * collides every node and stores each post-collision population in the
+ * node's slot of the opposite direction; an odd step pulls those from the
+ * neighbours, collides and pushes the results into the neighbours' natural
+ * slots.  Same bytes per node update and same results (to rounding) as the
+ * two-buffer form.  Differences: the buffer holds PRE-collision populations
+ * (time t, before its collision), so clbm_populations returns those;
+ * clbm_init_* store the initial populations without colliding them;
+ * clbm_step accepts even step counts only (EINVAL otherwise); one step per
+ * launch (fuse_steps = 2 is refused).  Velocities from clbm_macroscopic and
+ * clbm_reduce are the same physical quantities as in the two-buffer form. */
+clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out);
+
 /* Rest initial state f = w (rho = 1, u = 0), collided once so the buffer
  * holds post-collision populations (time 0). */
 clbm_status clbm_init_rest(clbm_lattice *h, void *stream);

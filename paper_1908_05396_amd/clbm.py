@@ -69,6 +69,7 @@ SIGNATURES = {
     "clbm_params_default": (ctypes.c_int, [_PP]),
     "clbm_buffer_size": (ctypes.c_int, [_PP, _I64P, ctypes.POINTER(ctypes.c_size_t)]),
     "clbm_create": (ctypes.c_int, [_PP, _VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    "clbm_create_in_place": (ctypes.c_int, [_PP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
     "clbm_init_rest": (ctypes.c_int, [_VP, _VP]),
     "clbm_init_populations": (ctypes.c_int, [_VP, _VP, _VP]),
     "clbm_step": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
@@ -194,18 +195,25 @@ class Lattice:
     handle, and thin wrappers of the C calls."""
 
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
-                 block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto"):
+                 block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto",
+                 in_place: bool = False):
         lib = load()
         self.spec = spec
         self.storage = storage
+        self.in_place = bool(in_place)
         self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision)
         self.plane, self.nbytes = buffer_size(self.params)
         self.device = torch.device(device)
-        self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        nbuf = 1 if self.in_place else 2
+        self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(nbuf)]
         h = ctypes.c_void_p()
-        _check(lib.clbm_create(ctypes.byref(self.params), ctypes.c_void_p(self.buffers[0].data_ptr()),
-                               ctypes.c_void_p(self.buffers[1].data_ptr()), ctypes.c_size_t(self.nbytes),
-                               ctypes.byref(h)))
+        if self.in_place:
+            _check(lib.clbm_create_in_place(ctypes.byref(self.params), ctypes.c_void_p(self.buffers[0].data_ptr()),
+                                            ctypes.c_size_t(self.nbytes), ctypes.byref(h)))
+        else:
+            _check(lib.clbm_create(ctypes.byref(self.params), ctypes.c_void_p(self.buffers[0].data_ptr()),
+                                   ctypes.c_void_p(self.buffers[1].data_ptr()), ctypes.c_size_t(self.nbytes),
+                                   ctypes.byref(h)))
         self._h = h
         if block is not None:
             self.set_block(*block)

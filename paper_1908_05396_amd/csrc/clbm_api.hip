@@ -1,5 +1,7 @@
 // C-ABI of the D3Q19 cascaded power-law LBM library (declared in clbm.h):
 // parameter validation, handles, kernel parameter set-up and launches.
+#include <array>
+
 #include "clbm_host.hpp"
 
 using namespace clbm;
@@ -15,6 +17,7 @@ struct clbm_lattice {
     Relax<float> rf;
     bool forced;
     int route;
+    bool in_place;          // one buffer, AA access pattern; stores pre-collision populations
     void *buf[2];
     size_t bytes_each;
     int cur;
@@ -36,6 +39,14 @@ struct clbm_lattice {
 // (18-37% more collisions); FP32 comes out even, FP16 (bound by arithmetic)
 // and FP64 (whose Newton solve dominates once the whole cavity moves) lose.
 // The two-step defaults below are the best measured shapes.
+// Velocity output subtracts F/2 from the momentum of the stored state: right
+// for post-collision populations (two-buffer form); the in-place form stores
+// pre-collision populations, whose momentum needs + F/2.
+static std::array<double, 3> output_force(const clbm_lattice *h, const double F[3]) {
+    const double s = h->in_place ? -1.0 : 1.0;
+    return {s * F[0], s * F[1], s * F[2]};
+}
+
 static void default_fusion(const clbm_params *p, StepLaunch *c) {
     const bool f64 = p->storage == CLBM_F64;
     c->fuse_steps = 1;
@@ -94,7 +105,8 @@ clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane, size_t *bytes
     return CLBM_OK;
 }
 
-clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, clbm_lattice **out) {
+static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, bool in_place,
+                                 clbm_lattice **out) {
     if (!out) return fail(CLBM_EINVAL, "out is NULL");
     *out = nullptr;
     clbm_status st = validate(p);
@@ -102,7 +114,7 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
     size_t need = 0;
     clbm_buffer_size(p, nullptr, &need);
     if (!pop_a || !pop_b) return fail(CLBM_EINVAL, "state buffers must not be NULL");
-    if (pop_a == pop_b) return fail(CLBM_EINVAL, "the two state buffers must differ");
+    if (pop_a == pop_b && !in_place) return fail(CLBM_EINVAL, "the two state buffers must differ");
     if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(CLBM_EINVAL, "state buffers must be 256-byte aligned");
     if (bytes_each < need)
         return fail(CLBM_EINVAL, "state buffers hold %zu bytes, need %zu", bytes_each, need);
@@ -115,6 +127,7 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
     h->rf = make_relax<float>(p);
     h->forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
     h->route = route_of(p);
+    h->in_place = in_place;
     h->buf[0] = pop_a;
     h->buf[1] = pop_b;
     h->bytes_each = bytes_each;
@@ -150,6 +163,14 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
     return CLBM_OK;
 }
 
+clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, clbm_lattice **out) {
+    return create_common(p, pop_a, pop_b, bytes_each, false, out);
+}
+
+clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out) {
+    return create_common(p, pop, pop, bytes, true, out);
+}
+
 clbm_status clbm_destroy(clbm_lattice *h) {
     if (!h) return CLBM_OK;
     if (h->partials) (void)hipFree(h->partials);
@@ -163,9 +184,13 @@ clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, void *strea
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     if (!f0) return fail(CLBM_EINVAL, "f0 is NULL");
     h->cur = 0;
-    HIP_TRY(launch_init(h->prm.storage, f0, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
-                        (hipStream_t)stream),
-            "clbm_init_populations");
+    if (h->in_place)
+        HIP_TRY(launch_store_plain(h->prm.storage, f0, h->buf[0], h->geom, (hipStream_t)stream),
+                "clbm_init_populations");
+    else
+        HIP_TRY(launch_init(h->prm.storage, f0, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
+                            (hipStream_t)stream),
+                "clbm_init_populations");
     h->initialized = true;
     h->steps_done = 0;
     h->have_snapshot = false;
@@ -175,10 +200,14 @@ clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, void *strea
 clbm_status clbm_init_rest(clbm_lattice *h, void *stream) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     h->cur = 0;
-    // f = w: every deviation is zero; the kernel collides that state once
-    HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
-                        (hipStream_t)stream),
-            "clbm_init_rest");
+    // f = w: every deviation is zero; the two-buffer form collides that state once
+    if (h->in_place)
+        HIP_TRY(launch_store_plain(h->prm.storage, nullptr, h->buf[0], h->geom, (hipStream_t)stream),
+                "clbm_init_rest");
+    else
+        HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
+                            (hipStream_t)stream),
+                "clbm_init_rest");
     h->initialized = true;
     h->steps_done = 0;
     h->have_snapshot = false;
@@ -190,6 +219,17 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
     if (!h->initialized) return fail(CLBM_ESTATE, "clbm_step before an init call");
     hipStream_t st = (hipStream_t)stream;
+    if (h->in_place) {
+        if (nsteps % 2) return fail(CLBM_EINVAL, "in-place lattices advance by even step counts (got %lld)",
+                                    (long long)nsteps);
+        for (int64_t t = 0; t < nsteps; t += 2) {
+            HIP_TRY(launch_aa_pair(h->prm.storage, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
+                                   h->launch, st),
+                    "clbm_step (in place)");
+            h->steps_done += 2;
+        }
+        return CLBM_OK;
+    }
     int64_t t = 0;
     if (h->launch.fuse_steps == 2) {
         for (; t + 2 <= nsteps; t += 2) {
@@ -214,7 +254,9 @@ clbm_status clbm_macroscopic(clbm_lattice *h, double *rho, double *u, void *stre
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     if (!h->initialized) return fail(CLBM_ESTATE, "clbm_macroscopic before an init call");
     if (!rho && !u) return CLBM_OK;
-    HIP_TRY(launch_macroscopic(h->prm.storage, h->buf[h->cur], rho, u, h->geom, h->prm.force, (hipStream_t)stream),
+    const double F[3] = {h->prm.force[0], h->prm.force[1], h->prm.force[2]};
+    HIP_TRY(launch_macroscopic(h->prm.storage, h->buf[h->cur], rho, u, h->geom, output_force(h, F).data(),
+                               (hipStream_t)stream),
             "clbm_macroscopic");
     return CLBM_OK;
 }
@@ -232,8 +274,9 @@ clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream) {
     if (!out) return fail(CLBM_EINVAL, "out is NULL");
     if (!h->initialized) return fail(CLBM_ESTATE, "clbm_reduce before an init call");
     hipStream_t st = (hipStream_t)stream;
+    const double F[3] = {h->prm.force[0], h->prm.force[1], h->prm.force[2]};
     HIP_TRY(launch_reduce(h->prm.storage, h->buf[h->cur], h->snapshot, h->have_snapshot ? 1 : 0, h->geom,
-                          h->prm.force, h->partials, h->nblocks, h->result, st),
+                          output_force(h, F).data(), h->partials, h->nblocks, h->result, st),
             "clbm_reduce");
     HIP_TRY(hipMemcpyAsync(h->host_result, h->result, sizeof(double) * kReduceSlots, hipMemcpyDeviceToHost, st),
             "clbm_reduce: copy");
@@ -269,6 +312,7 @@ clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
                          (c->fuse_rows == 12 && h->prm.storage == CLBM_F32);
     if (!rows_ok) return fail(CLBM_EINVAL, "fuse_rows must be 8, 16 (not FP64) or 12 (FP32 only)");
     if (c->fuse_planes < 1) return fail(CLBM_EINVAL, "fuse_planes must be >= 1");
+    if (c->fuse_steps == 2 && h->in_place) return fail(CLBM_EINVAL, "in-place lattices run one step per launch");
     if (c->fuse_steps == 2 && h->route == 2)
         return fail(CLBM_EINVAL, "the single-relaxation-time model runs one step per launch");
     if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
