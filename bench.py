@@ -91,11 +91,12 @@ def accuracy_vs(torch, runs, ref_key, U, L):
 OTHER_FORM = "other"
 
 
-def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None, keep_u=False, launch=None):
+def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None, keep_u=False, launch=None,
+                 in_place=False):
     """Run warmup + timed steps; returns timing and reduction results (and
     the final velocity field, FP64 on the device, if `keep_u`).  `launch`
     OTHER_FORM switches between one and two steps per launch."""
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block)
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place)
     if launch == OTHER_FORM:
         cur = lat.get_launch()
         if cur["fuse_steps"] == 1:
@@ -383,6 +384,16 @@ def main():
                       "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3)
                                              / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # one state buffer, stepped in place (AA pattern), FP32
+    in_place = None
+    if not args.no_variants:
+        r = time_lattice(clbm, torch, spec, "f32", 300, 20, args.reduce_every, in_place=True)
+        in_place = {"storage": "f32", "steps": 300, "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+                    "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
+                    "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3)
+                                           / 1e9 / HBM_PEAK_GBS, 4),
+                    "state_bytes": 1 * 19 * spec.nodes * 4}
+
     accuracy = None
     if compare:
         accuracy = accuracy_vs(torch, fields, "f64", spec.lid_velocity[0], args.size)
@@ -413,6 +424,7 @@ def main():
         "variants": variants,
         "other_launch_form": launch_forms,
         "srt_comparison": comparison,
+        "in_place": in_place,
         "accuracy": accuracy,
     }
     if not args.no_batch:
