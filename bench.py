@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=-1,
                     help="steps of the other storage variants (default: --steps + --warmup - 20, so that "
                          "all storages end at the same step and their velocity fields are compared)")
+    ap.add_argument("--variant-warmup", type=int, default=20,
+                    help="untimed steps before the timed steps of the FP16/FP64 variants")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
@@ -341,7 +343,7 @@ def main():
     workload = spec.name
 
     compare = not args.no_variants and args.variant_steps < 0
-    vsteps = args.steps + args.warmup - 20 if args.variant_steps < 0 else args.variant_steps
+    vsteps = args.steps + args.warmup - args.variant_warmup if args.variant_steps < 0 else args.variant_steps
     main_run = time_lattice(clbm, torch, spec, args.storage, args.steps, args.warmup, args.reduce_every,
                             keep_u=compare)
     mlups = spec.nodes * args.steps / (main_run["ms_per_step"] * args.steps * 1e-3) / 1e6
@@ -352,7 +354,7 @@ def main():
         for st in ("f16", "f64", "f32"):
             if st == args.storage:
                 continue
-            r = time_lattice(clbm, torch, spec, st, vsteps, 20, args.reduce_every, keep_u=compare)
+            r = time_lattice(clbm, torch, spec, st, vsteps, args.variant_warmup, args.reduce_every, keep_u=compare)
             fields[st] = r.pop("u", None)
             spl = r["launch"]["fuse_steps"]
             variants[st] = {

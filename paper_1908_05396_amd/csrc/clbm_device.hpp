@@ -159,7 +159,7 @@ template <> struct NewtonTol<float> {
 template <> struct NewtonTol<double> {
     static constexpr bool fixed = false;
     static constexpr int maxit = 16;
-    static constexpr double tol = 1e-9;     // one more step after this is exact to FP64
+    static constexpr double tol = 1e-9;     // the step that is this small lands exact to FP64
 };
 
 // FP32: the hardware log2/exp2/reciprocal (about 1 ulp); the arguments stay
@@ -209,7 +209,6 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
         if (!(s == s)) s = clampv(c + p.k * fast_log2(q0), p.s_lo, p.s_hi);   // FP32 range trouble
     }
     const T two_k = T(2) * p.k;
-    bool last = false;
     for (int it = 0; it < (NewtonTol<T>::fixed ? NI : NewtonTol<T>::maxit); ++it) {
         const T e = fast_exp2(s);                 // tau - 1/2
         const T it1 = fast_rcp(T(0.5) + e);       // 1/tau
@@ -224,8 +223,9 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
         }
         const T ds = sn - s;
         s = sn;
-        if (last) break;
-        if (fabs(ds) < NewtonTol<T>::tol) last = true;   // quadratic convergence: one more step
+        // quadratic convergence (phi is nearly linear in s, |phi''/phi'| = O(1)):
+        // after a step of size |ds| < tol the error is O(ds^2) < 1e-18
+        if (fabs(ds) < NewtonTol<T>::tol) break;
     }
     return clampv(T(0.5) + fast_exp2(s), p.tau_min, p.tau_max);
 }
