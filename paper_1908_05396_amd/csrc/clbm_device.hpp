@@ -697,6 +697,20 @@ __device__ inline void fix_edges(const S *__restrict__ A, const Geom &g, const R
     }
 }
 
+// Pull along a direction that leaves the lattice through an x face only (the
+// node is off the y and z faces): periodic x takes the far column, otherwise
+// half-way bounce-back, with the lid term when the lid is that x face.  The
+// same values as pull_edge, with the x face known.
+template <typename S, typename T>
+__device__ inline T pull_x_face(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int a, uint32_t self) {
+    if (g.px) {
+        const int jump = cx(a) == 1 ? g.nx - 1 : 1 - g.nx;
+        return (T)Plane<S>::load(A, g, a, self + (uint32_t)(jump - cy(a) * g.nx - cz(a) * g.nxy));
+    }
+    const bool in_lid = (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0;
+    return wall_value<T>((T)Plane<S>::load(A, g, opp(a), self), p, a, in_lid);
+}
+
 // Pull gather (Eq. cascaded streaming with the wall rules of Sec. 4).  Node
 // (x, y, z) receives along e_a the post-collision population that left
 // (x, y, z) - e_a.  Interior lanes read at a uniform offset per direction;
@@ -719,12 +733,12 @@ __device__ inline void gather(const S *__restrict__ A, const Geom &g, const Rela
         if (x == 0) {
 #pragma unroll
             for (int a = 1; a < Q; ++a)
-                if (cx(a) == 1) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+                if (cx(a) == 1) d[a] = pull_x_face<S, T>(A, g, p, a, self);
         }
         if (x == g.nx - 1) {
 #pragma unroll
             for (int a = 1; a < Q; ++a)
-                if (cx(a) == -1) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+                if (cx(a) == -1) d[a] = pull_x_face<S, T>(A, g, p, a, self);
         }
     }
 }
