@@ -116,6 +116,54 @@ template <int Aux> struct Plane<__half, Aux> {
     }
 };
 
+// Grouped access for the hot loop: G consecutive planes share one descriptor
+// whose range spans the G planes; the plane is selected by a uniform byte
+// offset added to the lane's offset, so the per-plane descriptors (four SGPRs
+// each) need not all be live.  Every address stays inside the group: offsets
+// past it return 0 (loads) or are dropped (stores), and a wrapped negative
+// offset lands in an earlier plane of the same group, whose value the edge
+// rule then replaces.  Valid when G planes span less than 4 GiB.
+template <typename S, int G> struct PlaneGroup {
+    __device__ static __amdgpu_buffer_rsrc_t rsrc(const S *A, const Geom &g, int a) {
+        const int k = a / G;
+        const int cnt = (Q - k * G) < G ? (Q - k * G) : G;
+        return __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + (int64_t)(k * G) * g.plane), (short)0,
+            (int)((uint32_t)cnt * (uint32_t)g.plane * (uint32_t)sizeof(S)), kBufferFlags);
+    }
+    // byte offset of plane a inside its group
+    __device__ static uint32_t offset(const Geom &g, int a) {
+        return (uint32_t)(a % G) * (uint32_t)g.plane * (uint32_t)sizeof(S);
+    }
+};
+
+template <typename S> struct RawBits;
+template <> struct RawBits<float> {
+    template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte, 0, Aux));
+    }
+    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte, 0, Aux);
+    }
+};
+template <> struct RawBits<__half> {
+    template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte) {
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte, 0, Aux)));
+    }
+    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, __float2half_rn(v)), r, (int)byte, 0, Aux);
+    }
+};
+template <> struct RawBits<double> {
+    template <int Aux> __device__ static double load(__amdgpu_buffer_rsrc_t r, uint32_t byte) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte, 0, Aux));
+    }
+    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, double v) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte, 0, Aux);
+    }
+};
+
 template <typename T> struct Relax {
     T lid6[3];              // 6 rho_w U_w: the moving-wall term is w_a (e_a . lid6)
     T log2_3K;              // log2(3 K)
@@ -724,6 +772,35 @@ __device__ inline void gather(const S *__restrict__ A, const Geom &g, const Rela
     for (int a = 0; a < Q; ++a) {
         const int off = -(cx(a) + cy(a) * g.nx + cz(a) * g.nxy);
         d[a] = (T)Plane<S, LdAux>::load(A, g, a, self + (uint32_t)off);
+    }
+    const bool yz_edge = y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1;
+    if (yz_edge) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) d[a] = pull_edge<S, T>(A, g, p, a, x, y, z, self);
+    } else {
+        if (x == 0) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                if (cx(a) == 1) d[a] = pull_x_face<S, T>(A, g, p, a, self);
+        }
+        if (x == g.nx - 1) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                if (cx(a) == -1) d[a] = pull_x_face<S, T>(A, g, p, a, self);
+        }
+    }
+}
+
+// gather() with the interior loads through grouped descriptors (PlaneGroup).
+template <typename S, typename T, int LdAux, int G>
+__device__ inline void gather_grouped(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
+                                      uint32_t self, T d[Q]) {
+    const uint32_t sb = self * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const uint32_t c = PlaneGroup<S, G>::offset(g, a) -
+                           (uint32_t)(cx(a) + cy(a) * g.nx + cz(a) * g.nxy) * (uint32_t)sizeof(S);
+        d[a] = (T)RawBits<S>::template load<LdAux>(PlaneGroup<S, G>::rsrc(A, g, a), sb + c);
     }
     const bool yz_edge = y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1;
     if (yz_edge) {

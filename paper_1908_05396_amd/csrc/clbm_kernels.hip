@@ -18,7 +18,9 @@ namespace clbm {
 // are dispatched round-robin to the eight XCDs; with `remap` set, workgroup b
 // takes the tile (b mod 8) * (B/8) + b / 8, so each XCD sweeps a contiguous
 // slab and the neighbour rows a node pulls from sit in the same L2.
-template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
+// G > 1: the interior loads and the stores go through descriptors shared by G
+// planes (PlaneGroup), when G planes span less than 4 GiB.
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, int G>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, LaunchGrid L) {
     uint32_t b = blockIdx.x;
@@ -32,10 +34,20 @@ stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<
     if (x >= g.nx || y >= g.ny) return;
     const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
     T d[Q];
-    gather<S, T, LdAux>(A, g, p, x, y, z, self, d);
-    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    if constexpr (G == 1) {
+        gather<S, T, LdAux>(A, g, p, x, y, z, self, d);
+        collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B, g, a, self, d[a]);
+        for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B, g, a, self, d[a]);
+    } else {
+        gather_grouped<S, T, LdAux, G>(A, g, p, x, y, z, self, d);
+        collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+        const uint32_t sb = self * (uint32_t)sizeof(S);
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            RawBits<S>::template store<StAux>(PlaneGroup<S, G>::rsrc(B, g, a), sb + PlaneGroup<S, G>::offset(g, a),
+                                              d[a]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -208,8 +220,25 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+template <typename S, typename T, bool Forced, int Route, int G>
+static hipError_t launch_step_g(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
+                                hipStream_t st);
+
+// planes per shared descriptor: 4 when four planes span less than 4 GiB
+template <typename S>
+static int plane_group(const Geom &g) {
+    return (uint64_t)g.plane * sizeof(S) * 4u <= 0xFFFFFFFFull ? 4 : 1;
+}
+
 template <typename S, typename T, bool Forced, int Route>
 static hipError_t launch_step_f(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
+                                hipStream_t st) {
+    return plane_group<S>(g) == 4 ? launch_step_g<S, T, Forced, Route, 4>(A, B, g, p, c, st)
+                                  : launch_step_g<S, T, Forced, Route, 1>(A, B, g, p, c, st);
+}
+
+template <typename S, typename T, bool Forced, int Route, int G>
+static hipError_t launch_step_g(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
                                 hipStream_t st) {
     LaunchGrid L;
     L.gx = (g.nx + c.bx - 1) / c.bx;
@@ -223,17 +252,17 @@ static hipError_t launch_step_f(const void *A, void *B, const Geom &g, const Rel
     S *b = (S *)B;
     if (Route == 1) {   // the printed form: only the store hint is tunable
         if (c.nt_stores)
-            hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2, Route>), grid, block, 0, st, a, b, g, p, L);
+            hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2, Route, G>), grid, block, 0, st, a, b, g, p, L);
         else
-            hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0, Route>), grid, block, 0, st, a, b, g, p, L);
+            hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0, Route, G>), grid, block, 0, st, a, b, g, p, L);
         return hipGetLastError();
     }
     const int mode = (c.nt_loads ? 1 : 0) | (c.nt_stores ? 2 : 0);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0, Route>), grid, block, 0, st, a, b, g, p, L); break;
-    case 1: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 0, Route>), grid, block, 0, st, a, b, g, p, L); break;
-    case 2: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2, Route>), grid, block, 0, st, a, b, g, p, L); break;
-    default: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 2, Route>), grid, block, 0, st, a, b, g, p, L); break;
+    case 0: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 0, Route, G>), grid, block, 0, st, a, b, g, p, L); break;
+    case 1: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 0, Route, G>), grid, block, 0, st, a, b, g, p, L); break;
+    case 2: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 0, 2, Route, G>), grid, block, 0, st, a, b, g, p, L); break;
+    default: hipLaunchKernelGGL((stream_collide_kernel<S, T, Forced, 2, 2, Route, G>), grid, block, 0, st, a, b, g, p, L); break;
     }
     return hipGetLastError();
 }
