@@ -26,7 +26,8 @@
  *   - State buffers hold, for each alpha, a plane of `plane_stride` values
  *     (>= nx*ny*nz, padded), structure of arrays: value(alpha, i) at
  *     element alpha*plane_stride + i.  Each value is the deviation
- *     f_alpha - w_alpha of the post-collision population from the rest
+ *     f_alpha - w_alpha of the post-collision population (pre-collision in
+ *     the one-buffer form of clbm_create_in_place) from the rest
  *     weight w = (1/3, 1/18 x 6, 1/36 x 12), stored as double (CLBM_F64),
  *     float (CLBM_F32) or IEEE half (CLBM_F16_DEV, round to nearest even).
  *     Arithmetic is double for CLBM_F64 and float otherwise.
@@ -66,12 +67,13 @@ typedef enum {
     CLBM_F16_DEV = 2  /* FP16 storage of f - w, FP32 arithmetic */
 } clbm_storage;
 
-/* Two algebraically equivalent forms of the collision (they agree to
- * rounding; see tests): the central-moment form relaxes each central-moment
+/* Two algebraically equivalent forms of the cascaded collision (they agree
+ * to rounding; see tests): the central-moment form relaxes each central-moment
  * combination and maps the raw-moment changes back to populations, and is
  * specialised to omega_9 = omega_10..18 = 1 (the paper's choice); the printed
  * form evaluates the changes of moments g4..g18 and f~ = f + K.g (Sec. 3.1,
- * 3.3) for any omega_9, omega_10..18. */
+ * 3.3) for any omega_9, omega_10..18.  A third value selects the paper's
+ * single-relaxation-time comparison model instead of its scheme. */
 typedef enum {
     CLBM_COLLIDE_AUTO = 0,     /* central-moment form when omega_9..18 are all 1, else printed form */
     CLBM_COLLIDE_CENTRAL = 1,  /* requires omega_9..18 = 1 */
@@ -152,26 +154,31 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
 clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out);
 
 /* Rest initial state f = w (rho = 1, u = 0), collided once so the buffer
- * holds post-collision populations (time 0). */
+ * holds post-collision populations (time 0; stored as is in the in-place
+ * form). */
 clbm_status clbm_init_rest(clbm_lattice *h, void *stream);
 
 /* Initial state from caller populations f0 (device memory, double, 19
  * planes of nx*ny*nz values, unpadded, alpha-major): collided once and stored
- * in the state's format.  f0 is only read. */
+ * in the state's format (the in-place form stores f0 itself).  f0 is only
+ * read. */
 clbm_status clbm_init_populations(clbm_lattice *h, const double *f0_dev, void *stream);
 
 /* Advance nsteps time steps (>= 0): one fused pull stream-collide launch per
- * step.  Asynchronous; no host synchronization. */
+ * step (two steps per launch with fuse_steps = 2; in the in-place form one
+ * launch per step and nsteps even).  Asynchronous; no host synchronization. */
 clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream);
 
 /* Density and velocity at the current time (device outputs, double,
  * unpadded): rho[i], u[c*N + i] for c = x, y, z.  Collision conserves mass
  * and momentum, so they are read from the stored post-collision populations:
- * rho = sum f, u = (sum e f - F/2)/rho.  Either pointer may be NULL. */
+ * rho = sum f, u = (sum e f - F/2)/rho (in-place form, pre-collision
+ * populations: u = (sum e f + F/2)/rho).  Either pointer may be NULL. */
 clbm_status clbm_macroscopic(clbm_lattice *h, double *rho_dev, double *u_dev, void *stream);
 
-/* Post-collision populations f = w + stored deviation, as double, 19 unpadded
- * planes (device output). */
+/* The stored populations f = w + stored deviation, as double, 19 unpadded
+ * planes (device output): post-collision, or pre-collision in the in-place
+ * form. */
 clbm_status clbm_populations(clbm_lattice *h, double *f_dev, void *stream);
 
 /* FP64 reductions over the lattice (synchronizes `stream`):
@@ -183,8 +190,9 @@ clbm_status clbm_populations(clbm_lattice *h, double *f_dev, void *stream);
  * Returns CLBM_EUNSTABLE (after filling out) if out[5] > 0. */
 clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream);
 
-/* Index (0 = pop_a, 1 = pop_b) of the buffer holding the current state, and
- * the number of steps taken since the last init. */
+/* Index (0 = pop_a, 1 = pop_b; always 0 in the in-place form) of the buffer
+ * holding the current state, and the number of steps taken since the last
+ * init. */
 clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done);
 
 /* Launch configuration of the stream-collide kernel (results do not depend
