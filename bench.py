@@ -36,7 +36,10 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 BYTES_PER_LUP = {"f64": 304, "f32": 152, "f16": 76}   # 19 reads + 19 writes per node update
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_05396_amd", "csrc", f)
-                  for f in ("clbm_device.hpp", "clbm_kernels.hip", "clbm_fused.hip")]
+                  for f in ("clbm_device.hpp", "clbm_internal.hpp", "clbm_kernels.hip", "clbm_rows.hip",
+                            "clbm_fused.hip")]
+# the one-step kernel of each state layout
+STEP_KERNEL = {"rows": "stream_collide_rows", "planes": "stream_collide"}
 
 
 def kernel_source_hash() -> str:
@@ -47,10 +50,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, workload: str):
+def measured_traffic(storage: str, workload: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this kernel and workload, or None if absent or taken on other sources."""
-    path = os.path.join(PROFILE_DIR, f"stream_collide_{workload}_{storage}_traffic.md")
+    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload}_{storage}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -92,18 +95,16 @@ OTHER_FORM = "other"
 
 
 def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None, keep_u=False, launch=None,
-                 in_place=False):
+                 in_place=False, layout=None):
     """Run warmup + timed steps; returns timing and reduction results (and
     the final velocity field, FP64 on the device, if `keep_u`).  `launch`
-    OTHER_FORM switches between one and two steps per launch."""
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place)
+    OTHER_FORM runs two steps per launch (planes layout) instead of one."""
+    form = None
     if launch == OTHER_FORM:
-        cur = lat.get_launch()
-        if cur["fuse_steps"] == 1:
-            lat.set_launch(fuse_steps=2, fuse_rows=8 if storage == "f64" else 16,
-                           fuse_planes=min(spec.nz, 32 if storage == "f64" else 8))
-        else:
-            lat.set_launch(fuse_steps=1)
+        form = {"fuse_steps": 2, "fuse_rows": 8 if storage == "f64" else 16,
+                "fuse_planes": min(spec.nz, 32 if storage == "f64" else 8)}
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place, launch=form,
+                       layout=layout)
     lat.init_rest()
     r0 = lat.reduce()
     lat.step(warmup)
@@ -137,6 +138,7 @@ def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=
         "nonfinite": r1["nonfinite"],
         "block": list(lat.get_block()),
         "launch": lat.get_launch(),
+        "layout": lat.layout,
     }
     if keep_u:
         out["u"] = lat.macroscopic()[1]
@@ -146,15 +148,16 @@ def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=
     return out
 
 
-def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch):
+def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch, layout):
     """HBM roofline of the stream-collide kernel: algorithmic bytes of one
     launch (19 reads + 19 writes per node and step, times the steps one
     launch advances) over the launch's average duration; `traffic` is the
     measured HBM bytes per launch from the committed counter summary."""
     achieved = BYTES_PER_LUP[storage] * nodes / (kernel_ms_per_step * 1e-3) / 1e9
+    kernel = STEP_KERNEL[layout] if steps_per_launch == 1 else "stream_collide2"
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(storage, workload),
+            "traffic": measured_traffic(storage, workload, kernel), "kernel": kernel,
             "bytes_per_lup": BYTES_PER_LUP[storage], "steps_per_launch": steps_per_launch}
 
 
@@ -359,7 +362,7 @@ def main():
             spl = r["launch"]["fuse_steps"]
             variants[st] = {
                 "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
-                "roofline": roofline(st, spec.nodes, r["kernel_ms_per_step"], workload, spl),
+                "roofline": roofline(st, spec.nodes, r["kernel_ms_per_step"], workload, spl, r["layout"]),
                 "kernel_ms_per_launch": round(r["kernel_ms_per_step"] * spl, 4),
                 "steps_per_launch": spl,
                 "mass_drift": r["mass_drift"], "steps": vsteps,
@@ -371,7 +374,19 @@ def main():
             r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, launch=OTHER_FORM)
             spl = r["launch"]["fuse_steps"]
             launch_forms[st] = {
-                "launch": r["launch"], "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+                "launch": r["launch"], "layout": r["layout"],
+                "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+                "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
+                "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS, 4)}
+
+    # the planes layout, one step per launch, for each storage
+    planes_layout = {}
+    if not args.no_variants:
+        for st in ("f32", "f16", "f64"):
+            r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, layout="planes")
+            planes_layout[st] = {
+                "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
                 "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
                 "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
                                        / HBM_PEAK_GBS, 4)}
@@ -418,13 +433,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "nodes": spec.nodes, "storage": args.storage,
                    "lid_velocity": spec.lid_velocity[0], "Re": 3200.0, "n": spec.n, "K": spec.K,
-                   "init": "rest", "reduce_every": args.reduce_every, "launch": main_run["launch"]},
+                   "init": "rest", "reduce_every": args.reduce_every, "layout": main_run["layout"],
+                   "launch": main_run["launch"]},
         "roofline": roofline(args.storage, spec.nodes, main_run["kernel_ms_per_step"], workload,
-                             main_run["launch"]["fuse_steps"]),
+                             main_run["launch"]["fuse_steps"], main_run["layout"]),
         "kernel_ms_per_launch": round(main_run["kernel_ms_per_step"] * main_run["launch"]["fuse_steps"], 4),
         "mass_drift": main_run["mass_drift"],
         "variants": variants,
         "other_launch_form": launch_forms,
+        "planes_layout": planes_layout,
         "srt_comparison": comparison,
         "in_place": in_place,
         "accuracy": accuracy,

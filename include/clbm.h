@@ -23,9 +23,12 @@
  *   - Node index i = x + nx*(y + ny*z) (x fastest).  Walls are not stored:
  *     they sit half-way between the outermost fluid node and a virtual ghost
  *     layer (half-way bounce-back, Sec. 4.1).
- *   - State buffers hold, for each alpha, a plane of `plane_stride` values
- *     (>= nx*ny*nz, padded), structure of arrays: value(alpha, i) at
- *     element alpha*plane_stride + i.  Each value is the deviation
+ *   - State buffers hold one value per (alpha, node) in one of two layouts
+ *     (clbm_layout).  Planes: for each alpha a plane of `plane_stride`
+ *     values (>= nx*ny*nz, padded), value(alpha, i) at element
+ *     alpha*plane_stride + i.  Rows: the 19 values of a lattice row (fixed
+ *     y, z) stored as 19 consecutive runs of nx, value(alpha, x, y, z) at
+ *     element ((y + ny*z)*19 + alpha)*nx + x.  Each value is the deviation
  *     f_alpha - w_alpha of the post-collision population (pre-collision in
  *     the one-buffer form of clbm_create_in_place) from the rest
  *     weight w = (1/3, 1/18 x 6, 1/36 x 12), stored as double (CLBM_F64),
@@ -83,6 +86,17 @@ typedef enum {
                                   stability comparisons; unforced, one step per launch, no batches */
 } clbm_collision;
 
+/* Layout of the state buffers (see Conventions).  Both hold the same values
+ * and give the same results; the row layout keeps the 19 populations of a row
+ * within 19*nx consecutive values, so one step reads 9 and writes 1 compact
+ * region per row instead of touching 38 planes far apart in memory, which
+ * DRAM serves faster.  The one-buffer form, two steps per launch and batches
+ * need planes. */
+typedef enum {
+    CLBM_LAYOUT_PLANES = 0,
+    CLBM_LAYOUT_ROWS = 1
+} clbm_layout;
+
 typedef enum {
     CLBM_LID_NONE = 0, CLBM_LID_MX = 1, CLBM_LID_PX = 2, CLBM_LID_MY = 3,
     CLBM_LID_PY = 4, CLBM_LID_MZ = 5, CLBM_LID_PZ = 6
@@ -102,6 +116,8 @@ typedef struct {
     int32_t plane_pad;         /* extra elements between population planes (>= 0), on top of the
                                   256-byte rounding; -1: library default (see clbm_buffer_size) */
     int32_t collision;         /* clbm_collision: which algebraic form of the collision runs */
+    int32_t layout;            /* clbm_layout of the state buffers */
+    int32_t reserved;          /* must be 0 */
     double K;                  /* consistency coefficient mu_p > 0 (Eq. 5) */
     double n;                  /* power-law index n > 0 (Eq. 5; n = 1 Newtonian) */
     double nu_min, nu_max;     /* clip of the apparent kinematic viscosity mu/rho,
@@ -121,15 +137,17 @@ typedef struct clbm_lattice clbm_lattice;
 
 /* Defaults: 1x1x1, no periodic axis, no lid, FP32 storage, normalized
  * attractors, residual tracking on, default plane padding, automatic
- * collision form, K = 0.01, n = 1, viscosity clip for omega in [0.1, 1.95],
+ * collision form, row layout, K = 0.01, n = 1, viscosity clip for omega in [0.1, 1.95],
  * omega_bulk = omega_high = 1, no force, rho_wall = 1. */
 clbm_status clbm_params_default(clbm_params *p);
 
-/* Elements per population plane for these dimensions and storage: nx*ny*nz
- * rounded up to 256 bytes, plus plane_pad elements (default: 256 bytes more
- * when the rounded plane is a multiple of 64 KiB, so the 19 planes do not all
- * start on the same HBM channel), and the bytes one state buffer needs (19
- * planes).  Either output pointer may be NULL. */
+/* Element stride between the values of populations alpha and alpha + 1 of
+ * a node, and the bytes one state buffer needs.  Planes: the stride is the
+ * plane, nx*ny*nz rounded up to 256 bytes, plus plane_pad elements (default:
+ * 256 bytes more when the rounded plane is a multiple of 64 KiB, so the 19
+ * planes do not all start on the same HBM channel); the buffer holds 19
+ * planes.  Rows: the stride is nx and the buffer holds 19*nx*ny*nz values
+ * (plane_pad unused).  Either output pointer may be NULL. */
 clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane_stride, size_t *bytes);
 
 /* Create a lattice over two caller-owned state buffers of `bytes_each` bytes
@@ -149,7 +167,8 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
  * (time t, before its collision), so clbm_populations returns those;
  * clbm_init_* store the initial populations without colliding them;
  * clbm_step accepts even step counts only (EINVAL otherwise); one step per
- * launch (fuse_steps = 2 is refused).  Velocities from clbm_macroscopic and
+ * launch (fuse_steps = 2 is refused); the planes layout only (EINVAL for
+ * rows).  Velocities from clbm_macroscopic and
  * clbm_reduce are the same physical quantities as in the two-buffer form. */
 clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out);
 
@@ -199,7 +218,9 @@ clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done);
  * on it; only speed does). */
 typedef struct {
     int32_t bx, by;      /* threads per block along x and y: bx*by at most 512 (FP32/FP16
-                            storage) or 256 (FP64); whole 64-lane waves run fastest */
+                            storage) or 256 (FP64); whole 64-lane waves run fastest (row
+                            layout: bx a multiple of 64 takes the fast kernel, other widths a
+                            kernel that applies the full wall rule on every lane) */
     int32_t xcd_remap;   /* 1: workgroup b takes tile (b mod 8)*(B/8) + b/8, so each of the
                             eight XCDs sweeps a contiguous slab of the lattice */
     int32_t nt_loads;    /* 1: non-temporal hint on population loads */
@@ -209,7 +230,7 @@ typedef struct {
                             its one-node ring, keeps it on chip and writes the second step of
                             the inner 62 x (fuse_rows - 2) columns, marching along z; the
                             result equals two one-step launches).  clbm_step runs an odd
-                            remainder as one one-step launch */
+                            remainder as one one-step launch.  Planes layout only */
     int32_t fuse_rows;   /* rows of a two-step workgroup, ring included: 8, 16 (not FP64), or
                             12 (FP32: the next plane's loads go straight to LDS) */
     int32_t fuse_planes; /* output z planes per two-step workgroup, >= 1 */
@@ -232,9 +253,10 @@ const char *clbm_last_error(void);
  * Batches: many independent lattices (uneven sizes, Re, n, lids, forces)
  * advanced together, one persistent launch per time step whose workgroups
  * stride over the tiles of all instances; k steps are captured into a
- * hipGraph and replayed.  All instances share the storage type.  Instance i
- * occupies 19 planes (clbm_buffer_size of its params) at a 256-byte-aligned
- * offset of each pool, in instance order.
+ * hipGraph and replayed.  All instances share the storage type and use the
+ * planes layout (EINVAL otherwise).  Instance i occupies 19 planes
+ * (clbm_buffer_size of its params) at a 256-byte-aligned offset of each pool,
+ * in instance order.
  * ------------------------------------------------------------------------ */
 typedef struct clbm_batch clbm_batch;
 

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libclbm.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("clbm_api.hip", "clbm_kernels.hip", "clbm_fused.hip", "clbm_inplace.hip", "clbm_batch.hip")]
+           for f in ("clbm_api.hip", "clbm_kernels.hip", "clbm_rows.hip", "clbm_fused.hip", "clbm_inplace.hip",
+                     "clbm_batch.hip")]
 
 # Packed FP32 instructions are disabled for every device compilation.
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -17,6 +17,7 @@ LIBPATH = os.path.join(_HERE, "libclbm.so")
 Q = 19
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 COLLISION = {"auto": 0, "central": 1, "ghat": 2, "srt": 3}
+LAYOUT = {"planes": 0, "rows": 1}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
 
 CLBM_OK, CLBM_EINVAL, CLBM_ENOMEM, CLBM_EHIP, CLBM_EUNSTABLE, CLBM_ESTATE = 0, -1, -2, -3, -4, -5
@@ -38,6 +39,8 @@ class Params(ctypes.Structure):
         ("track_residual", ctypes.c_int32),
         ("plane_pad", ctypes.c_int32),
         ("collision", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("K", ctypes.c_double), ("n", ctypes.c_double),
         ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
         ("omega_bulk", ctypes.c_double),
@@ -150,7 +153,7 @@ def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
 
 
 def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, plane_pad: int = -1,
-                     collision: str = "auto") -> Params:
+                     collision: str = "auto", layout: str = "rows") -> Params:
     """Fill the C parameter struct from a problem description with the
     attributes of workloads.LatticeSpec."""
     p = Params()
@@ -168,6 +171,7 @@ def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, pl
     if getattr(spec, "model", "cascaded") == "srt":
         collision = "srt"
     p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
+    p.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)
     p.K, p.n = float(spec.K), float(spec.n)
     p.nu_min, p.nu_max = float(spec.nu_min), float(spec.nu_max)
     p.omega_bulk = float(spec.omega_bulk)
@@ -196,12 +200,18 @@ class Lattice:
 
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
                  block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto",
-                 in_place: bool = False):
+                 in_place: bool = False, layout: str = None):
+        """layout: "rows" or "planes"; None picks planes for the one-buffer
+        form and for two steps per launch (which need them), rows otherwise."""
         lib = load()
         self.spec = spec
         self.storage = storage
         self.in_place = bool(in_place)
-        self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision)
+        if layout is None:
+            two_step = bool(launch) and int(launch.get("fuse_steps", 1)) == 2
+            layout = "planes" if (self.in_place or two_step) else "rows"
+        self.layout = layout
+        self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision, layout)
         self.plane, self.nbytes = buffer_size(self.params)
         self.device = torch.device(device)
         nbuf = 1 if self.in_place else 2
@@ -262,10 +272,24 @@ class Lattice:
         return idx.value, steps.value
 
     def state_tensor(self) -> torch.Tensor:
-        """The current state buffer as (19, plane_stride) deviations f - w."""
+        """The current state buffer of a planes-layout lattice as
+        (19, plane_stride) deviations f - w."""
+        if self.layout != "planes":
+            raise ValueError("state_tensor: planes layout only (state_view works for both)")
         idx, _ = self.state()
         dt = STORAGE_DTYPE[self.params.storage]
         return self.buffers[idx].view(dt).view(Q, self.plane)
+
+    def state_view(self) -> torch.Tensor:
+        """The current state buffer as a (19, nz, ny, nx) view of the stored
+        deviations f - w, in either layout (no copy)."""
+        idx, _ = self.state()
+        dt = STORAGE_DTYPE[self.params.storage]
+        nz, ny, nx = self.shape
+        flat = self.buffers[idx].view(dt)
+        if self.layout == "planes":
+            return flat[:Q * self.plane].view(Q, self.plane)[:, :self.nodes].view(Q, nz, ny, nx)
+        return flat[:Q * self.nodes].view(nz, ny, Q, nx).permute(2, 0, 1, 3)
 
     # -- outputs -----------------------------------------------------------
     def macroscopic(self, stream=None):
@@ -322,7 +346,7 @@ class Batch:
         n = len(self.specs)
         arr = (Params * n)()
         for i, sp in enumerate(self.specs):
-            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision)
+            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision, "planes")
         self._params = arr
         nbytes = ctypes.c_size_t()
         _check(lib.clbm_batch_size(arr, n, ctypes.byref(nbytes)))

@@ -86,6 +86,7 @@ clbm_status clbm_params_default(clbm_params *p) {
     p->storage = CLBM_F32;
     p->track_residual = 1;
     p->plane_pad = -1;
+    p->layout = CLBM_LAYOUT_ROWS;
     p->K = 0.01;
     p->n = 1.0;
     p->nu_min = (1.0 / 1.95 - 0.5) / 3.0;
@@ -101,7 +102,7 @@ clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane, size_t *bytes
     if (st != CLBM_OK) return st;
     const int64_t ps = plane_stride_of(p);
     if (plane) *plane = ps;
-    if (bytes) *bytes = (size_t)ps * Q * elem_bytes(p->storage);
+    if (bytes) *bytes = state_bytes_of(p);
     return CLBM_OK;
 }
 
@@ -115,6 +116,8 @@ static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b,
     clbm_buffer_size(p, nullptr, &need);
     if (!pop_a || !pop_b) return fail(CLBM_EINVAL, "state buffers must not be NULL");
     if (pop_a == pop_b && !in_place) return fail(CLBM_EINVAL, "the two state buffers must differ");
+    if (in_place && p->layout != CLBM_LAYOUT_PLANES)
+        return fail(CLBM_EINVAL, "the one-buffer form uses the planes layout");
     if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(CLBM_EINVAL, "state buffers must be 256-byte aligned");
     if (bytes_each < need)
         return fail(CLBM_EINVAL, "state buffers hold %zu bytes, need %zu", bytes_each, need);
@@ -132,16 +135,20 @@ static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b,
     h->buf[1] = pop_b;
     h->bytes_each = bytes_each;
     h->cur = 0;
-    // default launch shape: 64-wide rows, several rows per block
     // default launch: up to 256 threads along x (whole 64-wide waves), rows
     // stacked along y when the lattice is narrow
     int bx = p->nx >= 256 ? 256 : (p->nx >= 64 ? 64 * (p->nx / 64) : p->nx);
     if (bx > 256) bx = 256;
+    // row layout (512^3 cavity, MI355X): 256-wide blocks (FP64: 128) in
+    // XCD-contiguous order run 1-6% faster than the dispatch order
+    const bool rows = p->layout == CLBM_LAYOUT_ROWS;
+    if (rows && p->storage == CLBM_F64 && bx > 128) bx = 128;
     int by = 1;
-    while (bx * by * 2 <= 256 && by * 2 <= p->ny) by *= 2;
+    const int threads = (rows && p->nx >= 64) ? bx : 256;   // rows: one lattice row per block
+    while (bx * by * 2 <= threads && by * 2 <= p->ny) by *= 2;
     h->launch.bx = bx;
     h->launch.by = by;
-    h->launch.xcd_remap = 0;
+    h->launch.xcd_remap = rows ? 1 : 0;
     h->launch.nt_loads = 0;
     h->launch.nt_stores = 1;    // streaming stores: the new state is not re-read this step
     default_fusion(p, &h->launch);
@@ -241,9 +248,14 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
         }
     }
     for (; t < nsteps; ++t) {
-        HIP_TRY(launch_step(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf, h->forced,
-                            h->route, h->launch, st),
-                "clbm_step");
+        if (h->geom.rows)
+            HIP_TRY(launch_step_rows(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf,
+                                     h->forced, h->route, h->launch, st),
+                    "clbm_step");
+        else
+            HIP_TRY(launch_step(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf,
+                                h->forced, h->route, h->launch, st),
+                    "clbm_step");
         h->cur = 1 - h->cur;
         h->steps_done++;
     }
@@ -313,6 +325,8 @@ clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
     if (!rows_ok) return fail(CLBM_EINVAL, "fuse_rows must be 8, 16 (not FP64) or 12 (FP32 only)");
     if (c->fuse_planes < 1) return fail(CLBM_EINVAL, "fuse_planes must be >= 1");
     if (c->fuse_steps == 2 && h->in_place) return fail(CLBM_EINVAL, "in-place lattices run one step per launch");
+    if (c->fuse_steps == 2 && h->geom.rows)
+        return fail(CLBM_EINVAL, "two steps per launch need the planes layout");
     if (c->fuse_steps == 2 && h->route == 2)
         return fail(CLBM_EINVAL, "the single-relaxation-time model runs one step per launch");
     if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");

@@ -127,7 +127,7 @@ struct clbm_batch {
 namespace {
 
 size_t instance_bytes(const clbm_params *p) {
-    return (size_t)plane_stride_of(p) * Q * elem_bytes(p->storage);
+    return state_bytes_of(p);
 }
 
 void drop_graphs(clbm_batch *b) {
@@ -291,6 +291,8 @@ clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *byte
         if (inst[i].storage != inst[0].storage) return fail(CLBM_EINVAL, "instance %d: storage differs", i);
         if (inst[i].collision == CLBM_COLLIDE_SRT)
             return fail(CLBM_EINVAL, "instance %d: batches run the cascaded scheme only", i);
+        if (inst[i].layout != CLBM_LAYOUT_PLANES)
+            return fail(CLBM_EINVAL, "instance %d: batches use the planes layout", i);
         // the row of a node within its layer comes from a float estimate with
         // one correction, exact while a layer has at most 2^22 nodes
         if ((int64_t)inst[i].nx * inst[i].ny > ((int64_t)1 << 22))

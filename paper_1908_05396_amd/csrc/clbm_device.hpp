@@ -64,8 +64,22 @@ struct Geom {
     int32_t lid_axis;       // 0, 1, 2, or -1 for no lid
     int32_t lid_side;       // +1: the ghost plane beyond n-1; -1: the one before 0
     int32_t lid_mask;       // bit f-1 set for lid face f (1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z)
-    int64_t plane;          // elements per population plane
+    int32_t rows;           // 1: row layout, 0: planes
+    int64_t plane;          // element stride between populations a and a + 1 of a node
+    int64_t row;            // element stride between rows y and y + 1 (planes: nx, rows: 19 nx)
 };
+
+// Element index of population a of node (x, y, z) in either layout: planes
+// (plane = padded plane, row = nx) or rows (plane = nx, row = 19 nx).
+__host__ __device__ inline int64_t elem(const Geom &g, int a, int x, int y, int z) {
+    return (int64_t)a * g.plane + x + g.row * ((int64_t)z * g.ny + y);
+}
+// The same for node index i = x + nx (y + ny z) (i < 2^31).
+__device__ inline int64_t elem_i(const Geom &g, int a, int64_t i) {
+    const uint32_t r = (uint32_t)i / (uint32_t)g.nx;
+    const uint32_t x = (uint32_t)i - r * (uint32_t)g.nx;
+    return (int64_t)a * g.plane + x + g.row * (int64_t)r;
+}
 
 // ---------------------------------------------------------------------------
 // Plane access through raw buffer descriptors: one descriptor per population

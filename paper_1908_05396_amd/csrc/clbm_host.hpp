@@ -42,7 +42,10 @@ inline clbm_status hip_fail(hipError_t e, const char *what) {
 
 inline size_t elem_bytes(int storage) { return storage == CLBM_F64 ? 8 : (storage == CLBM_F32 ? 4 : 2); }
 
+// Element stride between populations a and a + 1 of a node: the padded plane
+// (planes layout) or nx (rows layout).
 inline int64_t plane_stride_of(const clbm_params *p) {
+    if (p->layout == CLBM_LAYOUT_ROWS) return p->nx;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t align = 256 / (int64_t)elem_bytes(p->storage);   // elements per 256 B
     int64_t plane = (N + align - 1) / align * align;
@@ -52,6 +55,12 @@ inline int64_t plane_stride_of(const clbm_params *p) {
         plane += align;
     }
     return plane;
+}
+
+// Bytes of one state buffer: 19 planes, or 19 values per node in rows.
+inline size_t state_bytes_of(const clbm_params *p) {
+    const int64_t per_pop = p->layout == CLBM_LAYOUT_ROWS ? (int64_t)p->nx * p->ny * p->nz : plane_stride_of(p);
+    return (size_t)per_pop * Q * elem_bytes(p->storage);
 }
 
 inline bool unit_high_omegas(const clbm_params *p) {
@@ -75,10 +84,15 @@ inline clbm_status validate(const clbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     if (p->storage < CLBM_F64 || p->storage > CLBM_F16_DEV)
         return fail(CLBM_EINVAL, "unknown storage %d", p->storage);
+    if (p->layout != CLBM_LAYOUT_PLANES && p->layout != CLBM_LAYOUT_ROWS)
+        return fail(CLBM_EINVAL, "unknown layout %d", p->layout);
+    if (p->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
     // one population plane is addressed through a buffer descriptor with a
-    // 32-bit byte range
-    if (N * (int64_t)elem_bytes(p->storage) > ((int64_t)1 << 32) - 256)
+    // 32-bit byte range; node indices are 32-bit in either layout
+    if (p->layout == CLBM_LAYOUT_PLANES && N * (int64_t)elem_bytes(p->storage) > ((int64_t)1 << 32) - 256)
         return fail(CLBM_EINVAL, "lattice of %lld nodes: one population plane exceeds 4 GiB", (long long)N);
+    if (N >= ((int64_t)1 << 31))
+        return fail(CLBM_EINVAL, "lattice of %lld nodes: at most 2^31 - 1 nodes", (long long)N);
     if (!(p->K > 0.0) || !isfinite(p->K)) return fail(CLBM_EINVAL, "K must be finite and > 0");
     if (!(p->n > 0.0) || !isfinite(p->n)) return fail(CLBM_EINVAL, "n must be finite and > 0");
     if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min) || !isfinite(p->nu_max))
@@ -144,6 +158,8 @@ inline Geom make_geom(const clbm_params *p) {
         g.lid_mask = 1 << (p->lid_face - 1);
     }
     g.plane = plane_stride_of(p);
+    g.rows = p->layout == CLBM_LAYOUT_ROWS;
+    g.row = g.rows ? (int64_t)Q * p->nx : (int64_t)p->nx;
     return g;
 }
 

@@ -34,6 +34,8 @@ constexpr int kReduceSlots = 9;
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                        const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
+hipError_t launch_step_rows(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
+                            const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
 hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                         const Relax<float> &pf, bool forced, int route, int rows, int planes, hipStream_t st);
 hipError_t launch_aa_pair(int storage, void *A, const Geom &g, const Relax<double> &pd, const Relax<float> &pf,

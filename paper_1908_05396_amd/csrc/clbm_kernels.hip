@@ -65,20 +65,20 @@ init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Re
     for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) Plane<S>::store(B, g, a, (uint32_t)i, d[a]);
+    for (int a = 0; a < Q; ++a) B[elem_i(g, a, i)] = Conv<S, T>::store(d[a]);
 }
 
 // ---------------------------------------------------------------------------
 // Moments of the stored state
 // ---------------------------------------------------------------------------
 template <typename S>
-__device__ inline void node_moments(const S *__restrict__ A, int64_t plane, int64_t i, double &D,
+__device__ inline void node_moments(const S *__restrict__ A, const Geom &g, int64_t i, double &D,
                                     double &jx, double &jy, double &jz, bool &finite) {
     D = jx = jy = jz = 0.0;
     finite = true;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-        double v = (double)Conv<S, typename StoreCompute<S>::T>::load(A[(int64_t)a * plane + i]);
+        double v = (double)Conv<S, typename StoreCompute<S>::T>::load(A[elem_i(g, a, i)]);
         finite = finite && isfinite(v);
         D += v;
         jx += cx(a) * v;
@@ -96,7 +96,7 @@ macroscopic_kernel(const S *__restrict__ A, double *__restrict__ rho, double *__
     if (i >= N) return;
     double D, jx, jy, jz;
     bool finite;
-    node_moments(A, g.plane, i, D, jx, jy, jz, finite);
+    node_moments(A, g, i, D, jx, jy, jz, finite);
     const double r = 1.0 + D;
     if (rho) rho[i] = r;
     if (u) {
@@ -115,7 +115,7 @@ export_kernel(const S *__restrict__ A, double *__restrict__ f, Geom g) {
 #pragma unroll
     for (int a = 0; a < Q; ++a)
         f[(int64_t)a * N + i] =
-            weight(a) + (double)Conv<S, typename StoreCompute<S>::T>::load(A[(int64_t)a * g.plane + i]);
+            weight(a) + (double)Conv<S, typename StoreCompute<S>::T>::load(A[elem_i(g, a, i)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,7 +144,7 @@ reduce_kernel(const S *__restrict__ A, float *__restrict__ snap, int have_prev, 
          i += (int64_t)gridDim.x * blockDim.x) {
         double D, jx, jy, jz;
         bool finite;
-        node_moments(A, g.plane, i, D, jx, jy, jz, finite);
+        node_moments(A, g, i, D, jx, jy, jz, finite);
         const double r = 1.0 + D;
         const double mx = jx - 0.5 * fx, my = jy - 0.5 * fy, mz = jz - 0.5 * fz;
         const double ux = mx / r, uy = my / r, uz = mz / r;

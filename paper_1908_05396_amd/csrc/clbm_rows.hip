@@ -1,0 +1,280 @@
+// One time step on the row layout: the 19 populations of lattice row
+// r = y + ny z are stored as 19 consecutive runs of nx values, population a
+// of node x at element (19 r + a) nx + x.
+//
+// A step then reads, for every row, parts of the 9 row groups r - e_y - ny e_z
+// and writes one row group: a few compact regions instead of 38 planes spread
+// over the whole buffer, which keeps the DRAM page and bank traffic of
+// neighbouring waves together.
+//
+//   stream_collide_rows       rows off the y and z faces.  Each wave covers
+//                             64 consecutive x of one row (blockDim.x a
+//                             multiple of 64), so the source of direction a
+//                             is a uniform address plus the lane's x: one
+//                             scalar base per load and store, one shared
+//                             lane offset; only the lanes on an x face take a
+//                             wall rule.
+//   stream_collide_rows_face  the rows on a y or z face (about 6/L of an L^3
+//                             lattice), launched after the first kernel: per
+//                             direction, uniformly, a source row inside,
+//                             wrapped, or a ghost (bounce-back).  Keeping them
+//                             apart keeps the first kernel's scalar registers
+//                             low enough for eight waves per SIMD.
+//   stream_collide_any        any block shape: the full rule on every lane
+//                             (narrow lattices).
+#include "clbm_internal.hpp"
+
+namespace clbm {
+
+namespace {
+
+// Pull along e_a with the full wall logic (Eq. cascaded streaming with the
+// rules of Sec. 4), in either layout: periodic wrap, half-way bounce-back,
+// moving lid.  a = 0 returns the node's own rest population.
+template <typename S, typename T>
+__device__ inline T pull_any(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int a, int x, int y, int z) {
+    int sx = x - cx(a), sy = y - cy(a), sz = z - cz(a);
+    const bool in_lid = ghost_in_lid(g, sx, sy, sz);
+    bool wall = false;
+    if (sx < 0 || sx >= g.nx) { if (g.px) sx = sx < 0 ? sx + g.nx : sx - g.nx; else wall = true; }
+    if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
+    if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
+    if (!wall) return (T)Conv<S, T>::load(A[elem(g, a, sx, sy, sz)]);
+    return wall_value<T>((T)Conv<S, T>::load(A[elem(g, opp(a), x, y, z)]), p, a, in_lid);
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
+}
+
+__device__ inline void tile_of(const LaunchGrid &L, uint32_t &tx, uint32_t &ty, int &z) {
+    uint32_t b = blockIdx.x;
+    if (L.remap && b < L.aligned) b = (b & 7u) * (L.aligned >> 3) + (b >> 3);
+    tx = b % L.gx;
+    b /= L.gx;
+    ty = b % L.gy;
+    z = (int)(b / L.gy);
+}
+
+}  // namespace
+
+// Node x of row (y, z), y and z uniform over the wave; Face: the row lies on
+// a y or z face.
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face>
+__device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p, int x,
+                                int y, int z) {
+    constexpr uint32_t es = sizeof(S);
+    const int64_t r = (int64_t)z * g.ny + y;
+    // Each direction reads a run of its source row through a base one value
+    // before the run; the lane offset selects x - cx(a) + 1, wrapped on a
+    // periodic x axis.  Offsets stay within nx + 2 values of the base, and
+    // every address lies inside the buffer (x - cx(a) = -1 or nx reaches the
+    // neighbouring run of the same row group, which the x-face rule below
+    // replaces).
+    // (the ranges pass through readfirstlane so that the compiler keeps the
+    // descriptors in scalar registers)
+    const uint32_t range = __builtin_amdgcn_readfirstlane((uint32_t)(g.nx + 2) * es);
+    const uint32_t o0 = (uint32_t)(x + 1) * es;
+    const uint32_t op = (g.px && x == 0) ? range - 2 * es : (uint32_t)x * es;      // cx = +1: source x - 1
+    const uint32_t om = (g.px && x == g.nx - 1) ? es : (uint32_t)(x + 2) * es;     // cx = -1: source x + 1
+    auto lane_off = [&](int a) { return cx(a) == 1 ? op : (cx(a) == -1 ? om : o0); };
+    auto run = [&](int a, int64_t row) {
+        return row_rsrc(A + row * g.row + (int64_t)a * g.nx - 1, range);
+    };
+    // the node's own row group, for the bounce-back values (slot in the lane offset)
+    const __amdgpu_buffer_rsrc_t own_rsrc =
+        row_rsrc(A + r * g.row, __builtin_amdgcn_readfirstlane((uint32_t)Q * (uint32_t)g.nx * es));
+    auto own = [&](int a) {
+        return (T)RawBits<S>::template load<LdAux>(own_rsrc, (uint32_t)(opp(a) * g.nx + x) * es);
+    };
+    T d[Q];
+    if constexpr (!Face) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            d[a] = (T)RawBits<S>::template load<LdAux>(run(a, r - cy(a) - (int64_t)cz(a) * g.ny), lane_off(a));
+    } else {
+        // rows on a y or z face: per direction (uniformly) the source row is
+        // inside, wrapped on a periodic axis, or a ghost: half-way bounce-back
+        // returns the node's own population opposite to a, plus the
+        // moving-wall term for a ghost in the lid plane
+        const int m = g.lid_mask;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            int sy = y - cy(a), sz = z - cz(a);
+            bool wall = false;
+            if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
+            if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
+            if (!wall) {
+                d[a] = (T)RawBits<S>::template load<LdAux>(run(a, (int64_t)sz * g.ny + sy), lane_off(a));
+            } else {
+                const int sx = x - cx(a);
+                const bool in_lid = ((m & 4) && sy == -1) || ((m & 8) && sy == g.ny) || ((m & 16) && sz == -1) ||
+                                    ((m & 32) && sz == g.nz) || ((m & 1) && sx == -1) || ((m & 2) && sx == g.nx);
+                d[a] = wall_value<T>(own(a), p, a, in_lid);
+            }
+        }
+    }
+    // lanes on a non-periodic x face: directions whose source row is inside
+    // the lattice but whose source column is a ghost
+    if (!g.px && (x == 0 || x == g.nx - 1)) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            if (cx(a) == 0 || !((x == 0 && cx(a) == 1) || (x == g.nx - 1 && cx(a) == -1))) continue;
+            const int sy = y - cy(a), sz = z - cz(a);
+            const bool row_wall = (!g.py && (sy < 0 || sy >= g.ny)) || (!g.pz && (sz < 0 || sz >= g.nz));
+            if (row_wall) continue;     // bounced back above, with the lid term of every ghost coordinate
+            d[a] = wall_value<T>(own(a), p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
+        }
+    }
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    const uint32_t srange = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
+    S *out = B + r * g.row;
+    const uint32_t lane = (uint32_t)x * es;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+        RawBits<S>::template store<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a]);
+}
+
+struct RowGrid {
+    uint32_t gx;            // tiles along x
+    uint32_t rows;          // rows handled by the launch
+    uint32_t aligned;       // largest multiple of 8 <= number of workgroups
+    int32_t remap;          // XCD-contiguous tile order
+    int32_t zf, yf;         // face rows: z faces (1 or 2) and y faces (1 or 2)
+};
+
+// Row index of the wave and tile of the workgroup (blockDim.x a multiple of 64).
+__device__ inline bool row_of(const RowGrid &R, int &x, uint32_t &ri) {
+    uint32_t b = blockIdx.x;
+    if (R.remap && b < R.aligned) b = (b & 7u) * (R.aligned >> 3) + (b >> 3);
+    const uint32_t tx = b % R.gx;
+    ri = __builtin_amdgcn_readfirstlane((b / R.gx) * blockDim.y + threadIdx.y);
+    x = (int)(tx * blockDim.x + threadIdx.x);
+    return ri < R.rows;
+}
+
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+stream_collide_rows_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, RowGrid R) {
+    int x;
+    uint32_t ri;
+    if (!row_of(R, x, ri) || x >= g.nx) return;
+    // inner rows: y in [1, ny - 2], z in [1, nz - 2]
+    const uint32_t w = (uint32_t)g.ny - 2u;
+    const int y = 1 + (int)(ri % w), z = 1 + (int)(ri / w);
+    row_step<S, T, Forced, LdAux, StAux, Route, false>(A, B, g, p, x, y, z);
+}
+
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+stream_collide_rows_face_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, RowGrid R) {
+    int x;
+    uint32_t ri;
+    if (!row_of(R, x, ri) || x >= g.nx) return;
+    // every row of the z faces, then the y-face rows of the inner z layers
+    int y, z;
+    const uint32_t nzr = (uint32_t)R.zf * (uint32_t)g.ny;
+    if (ri < nzr) {
+        y = (int)(ri % (uint32_t)g.ny);
+        z = ri < (uint32_t)g.ny ? 0 : g.nz - 1;
+    } else {
+        const uint32_t k = ri - nzr;
+        z = 1 + (int)(k / (uint32_t)R.yf);
+        y = (k % (uint32_t)R.yf) == 0 ? 0 : g.ny - 1;
+    }
+    row_step<S, T, Forced, LdAux, StAux, Route, true>(A, B, g, p, x, y, z);
+}
+
+template <typename S, typename T, bool Forced, int Route>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+stream_collide_any_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, LaunchGrid L) {
+    uint32_t tx, ty;
+    int z;
+    tile_of(L, tx, ty, z);
+    const int x = (int)(tx * blockDim.x + threadIdx.x);
+    const int y = (int)(ty * blockDim.y + threadIdx.y);
+    if (y >= g.ny || x >= g.nx) return;
+    T d[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) d[a] = pull_any<S, T>(A, g, p, a, x, y, z);
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) B[elem(g, a, x, y, z)] = Conv<S, T>::store(d[a]);
+}
+
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
+static hipError_t launch_rows_k(const S *a, S *b, const Geom &g, const Relax<T> &p, const StepLaunch &c,
+                                hipStream_t st) {
+    // inner rows, then the face rows
+    RowGrid R;
+    R.gx = (g.nx + c.bx - 1) / c.bx;
+    R.remap = c.xcd_remap;
+    R.zf = g.nz > 1 ? 2 : 1;
+    R.yf = g.ny > 1 ? 2 : 1;
+    const dim3 block(c.bx, c.by);
+    const uint32_t inner = (g.ny > 2 && g.nz > 2) ? (uint32_t)(g.ny - 2) * (uint32_t)(g.nz - 2) : 0u;
+    if (inner > 0) {
+        R.rows = inner;
+        const uint32_t nb = R.gx * ((inner + c.by - 1) / c.by);
+        R.aligned = nb & ~7u;
+        hipLaunchKernelGGL((stream_collide_rows_kernel<S, T, Forced, LdAux, StAux, Route>), dim3(nb), block, 0, st,
+                           a, b, g, p, R);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    R.rows = (uint32_t)R.zf * (uint32_t)g.ny + (g.nz > 2 ? (uint32_t)(g.nz - 2) * (uint32_t)R.yf : 0u);
+    const uint32_t nb = R.gx * ((R.rows + c.by - 1) / c.by);
+    R.aligned = nb & ~7u;
+    R.remap = 0;
+    hipLaunchKernelGGL((stream_collide_rows_face_kernel<S, T, Forced, LdAux, StAux, Route>), dim3(nb), block, 0, st,
+                       a, b, g, p, R);
+    return hipGetLastError();
+}
+
+template <typename S, typename T, bool Forced, int Route>
+static hipError_t launch_rows_f(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
+                                hipStream_t st) {
+    const S *a = (const S *)A;
+    S *b = (S *)B;
+    if (c.bx % 64 != 0) {
+        LaunchGrid L;
+        L.gx = (g.nx + c.bx - 1) / c.bx;
+        L.gy = (g.ny + c.by - 1) / c.by;
+        L.gz = g.nz;
+        const uint32_t nb = L.gx * L.gy * L.gz;
+        L.aligned = nb & ~7u;
+        L.remap = c.xcd_remap;
+        hipLaunchKernelGGL((stream_collide_any_kernel<S, T, Forced, Route>), dim3(nb), dim3(c.bx, c.by), 0, st, a, b,
+                           g, p, L);
+        return hipGetLastError();
+    }
+    if (Route != 0)     // the printed form and the comparison model: only the store hint is tunable
+        return c.nt_stores ? launch_rows_k<S, T, Forced, 0, 2, Route>(a, b, g, p, c, st)
+                           : launch_rows_k<S, T, Forced, 0, 0, Route>(a, b, g, p, c, st);
+    switch ((c.nt_loads ? 1 : 0) | (c.nt_stores ? 2 : 0)) {
+    case 0: return launch_rows_k<S, T, Forced, 0, 0, Route>(a, b, g, p, c, st);
+    case 1: return launch_rows_k<S, T, Forced, 2, 0, Route>(a, b, g, p, c, st);
+    case 2: return launch_rows_k<S, T, Forced, 0, 2, Route>(a, b, g, p, c, st);
+    default: return launch_rows_k<S, T, Forced, 2, 2, Route>(a, b, g, p, c, st);
+    }
+}
+
+template <typename S, typename T>
+static hipError_t launch_rows_t(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
+                                const StepLaunch &c, hipStream_t st) {
+    if (route == 2) return forced ? hipErrorInvalidValue : launch_rows_f<S, T, false, 2>(A, B, g, p, c, st);
+    if (route == 0)
+        return forced ? launch_rows_f<S, T, true, 0>(A, B, g, p, c, st) : launch_rows_f<S, T, false, 0>(A, B, g, p, c, st);
+    return forced ? launch_rows_f<S, T, true, 1>(A, B, g, p, c, st) : launch_rows_f<S, T, false, 1>(A, B, g, p, c, st);
+}
+
+hipError_t launch_step_rows(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
+                            const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_rows_t<double, double>(A, B, g, pd, forced, route, c, st);
+    case 1: return launch_rows_t<float, float>(A, B, g, pf, forced, route, c, st);
+    default: return launch_rows_t<__half, float>(A, B, g, pf, forced, route, c, st);
+    }
+}
+
+}  // namespace clbm

@@ -53,32 +53,36 @@ def test_kernel_tables_match_paper(clbm):
 
 
 def test_params_struct_layout(clbm):
-    assert ctypes.sizeof(clbm.Params) == 48 + 8 * (5 + 9 + 3 + 3 + 1)
+    assert ctypes.sizeof(clbm.Params) == 56 + 8 * (5 + 9 + 3 + 3 + 1)
     p = clbm.Params()
     assert clbm.load().clbm_params_default(ctypes.byref(p)) == 0
     assert (p.nx, p.ny, p.nz) == (1, 1, 1)
     assert p.storage == 1 and p.omega_bulk == 1.0 and p.rho_wall == 1.0
+    assert p.layout == clbm.LAYOUT["rows"] and p.reserved == 0
     assert list(p.omega_high) == [1.0] * 9
 
 
 @pytest.mark.parametrize("storage,esize", [("f64", 8), ("f32", 4), ("f16", 2)])
 def test_buffer_size_padding(clbm, storage, esize):
     spec = W.cavity(37, 0.05, 1.0, 100.0)
-    plane, nbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage))
+    plane, nbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage, layout="planes"))
     assert plane >= spec.nodes and (plane * esize) % 256 == 0 and plane * esize - spec.nodes * esize < 256
     # a plane of 2^k bytes gets 256 bytes of padding by default (HBM channel spread)
     pow2 = W.cavity(64, 0.05, 1.0, 100.0)
-    plane2, _ = clbm.buffer_size(clbm.params_from_spec(pow2, storage))
+    plane2, _ = clbm.buffer_size(clbm.params_from_spec(pow2, storage, layout="planes"))
     assert plane2 * esize == pow2.nodes * esize + 256
-    plane3, _ = clbm.buffer_size(clbm.params_from_spec(pow2, storage, plane_pad=0))
+    plane3, _ = clbm.buffer_size(clbm.params_from_spec(pow2, storage, plane_pad=0, layout="planes"))
     assert plane3 == pow2.nodes
     assert nbytes == 19 * plane * esize
+    # row layout: populations a and a + 1 of a node are nx apart, no padding
+    stride, rbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage, layout="rows"))
+    assert stride == spec.nx and rbytes == 19 * spec.nodes * esize
 
 
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("K", 0.0), ("K", float("nan")), ("n", -1.0), ("nu_min", 0.0), ("nu_max", 1e-6),
     ("omega_bulk", 2.0), ("rho_wall", 0.0), ("storage", 7), ("lid_face", 9), ("attractor_literal", 2),
-    ("collision", 4), ("plane_pad", -2),
+    ("collision", 4), ("plane_pad", -2), ("layout", 2), ("layout", -1), ("reserved", 1),
 ])
 def test_invalid_parameters_rejected(clbm, field, value):
     p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")
@@ -112,14 +116,17 @@ def test_batch_size_validates_each_instance(clbm):
     specs = [W.cavity(8, 0.05, 1.0, 10.0), W.cavity(12, 0.05, 0.7, 10.0)]
     arr = (clbm.Params * 2)()
     for i, sp in enumerate(specs):
-        arr[i] = clbm.params_from_spec(sp, "f32")
+        arr[i] = clbm.params_from_spec(sp, "f32", layout="planes")
     n = ctypes.c_size_t()
     assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == 0
     assert n.value == sum(clbm.buffer_size(arr[i])[1] for i in range(2))
     arr[1].storage = 0
     assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
     assert "instance 1" in clbm.load().clbm_last_error().decode()
-    arr[1] = clbm.params_from_spec(specs[1], "f32")
+    arr[1] = clbm.params_from_spec(specs[1], "f32", layout="rows")
+    assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
+    assert "planes layout" in clbm.load().clbm_last_error().decode()
+    arr[1] = clbm.params_from_spec(specs[1], "f32", layout="planes")
     arr[1].K = -1.0
     assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
     assert clbm.load().clbm_batch_size(arr, 0, ctypes.byref(n)) == clbm.CLBM_EINVAL
@@ -139,3 +146,28 @@ def test_srt_model_restrictions(clbm):
     arr[0] = p
     n = ctypes.c_size_t()
     assert clbm.load().clbm_batch_size(arr, 1, ctypes.byref(n)) == clbm.CLBM_EINVAL
+
+
+def test_row_layout_restrictions(clbm):
+    """The one-buffer form needs the planes layout; the check comes before any
+    device call."""
+    lib = clbm.load()
+    h = ctypes.c_void_p()
+    p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32", layout="rows")
+    assert lib.clbm_create_in_place(ctypes.byref(p), ctypes.c_void_p(0x1000), ctypes.c_size_t(1 << 30),
+                                    ctypes.byref(h)) == clbm.CLBM_EINVAL
+    assert "planes layout" in lib.clbm_last_error().decode()
+
+
+def test_size_limits_per_layout(clbm):
+    """Planes: one plane must fit the 4 GiB range of a buffer descriptor.
+    Rows: no plane limit, node indices are 32-bit (fewer than 2^31 nodes)."""
+    big = W.cavity(16, 0.05, 0.8, 100.0).with_(nx=1024, ny=1024, nz=1024)
+    with pytest.raises(clbm.ClbmError):
+        clbm.buffer_size(clbm.params_from_spec(big, "f32", layout="planes"))
+    stride, nbytes = clbm.buffer_size(clbm.params_from_spec(big, "f32", layout="rows"))
+    assert stride == 1024 and nbytes == 19 * 4 * 1024 ** 3
+    too_many = big.with_(nx=2048)
+    with pytest.raises(clbm.ClbmError):
+        clbm.buffer_size(clbm.params_from_spec(too_many, "f16", layout="rows"))
+    clbm.buffer_size(clbm.params_from_spec(too_many.with_(nz=1023), "f16", layout="rows"))

@@ -54,13 +54,15 @@ def _oracle_at(spec, seed, eps, pt, k):
     return u[:, iz, iy, ix], ft[:, iz, iy, ix]
 
 
-@pytest.mark.parametrize("config,storage", [("cavity512", "f32"), ("cavity512", "f16"), ("cavity512", "f64"),
-                                            ("cavity256", "f32"), ("cavity256", "f16")])
-def test_light_cone_samples(clbm, config, storage):
+@pytest.mark.parametrize("config,storage,layout", [
+    ("cavity512", "f32", "rows"), ("cavity512", "f16", "rows"), ("cavity512", "f64", "rows"),
+    ("cavity512", "f32", "planes"), ("cavity512", "f16", "planes"), ("cavity256", "f32", "rows"),
+    ("cavity256", "f16", "rows")])
+def test_light_cone_samples(clbm, config, storage, layout):
     spec = W.config_cavity512() if config == "cavity512" else W.config_cavity256()
     seed, eps = 77, 2e-3
-    print(f"[gpu] full-size {spec.name} {storage} k={K_STEPS}", flush=True)
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False)
+    print(f"[gpu] full-size {spec.name} {storage} {layout} k={K_STEPS}", flush=True)
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
     f0 = W.perturbed_populations(spec, seed, eps, device="cuda")
     lat.init_populations(f0)
     del f0
@@ -71,9 +73,8 @@ def test_light_cone_samples(clbm, config, storage):
     idx = torch.tensor([[p[2], p[1], p[0]] for p in pts], device="cuda")
     u_gpu = u[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().T
     del u
-    st = lat.state_tensor()
-    node = (idx[:, 0] * spec.ny + idx[:, 1]) * spec.nx + idx[:, 2]
-    d_gpu = st[:, node].to(torch.float64).cpu().numpy().T
+    st = lat.state_view()
+    d_gpu = st[:, idx[:, 0], idx[:, 1], idx[:, 2]].to(torch.float64).cpu().numpy().T
     lat.close()
     del lat, st
     torch.cuda.empty_cache()

@@ -55,7 +55,7 @@ def _run(clbm, spec, storage, steps, launch, seed=11, eps=1e-2, collision="auto"
     lat = clbm.Lattice(spec, storage=storage, track_residual=False, launch=launch, collision=collision)
     lat.init_populations(W.perturbed_populations(spec, seed, eps, device="cuda"))
     lat.step(steps)
-    st = lat.state_tensor()[:, :spec.nodes].clone()
+    st = lat.state_view().reshape(19, -1).clone()
     _, u = lat.macroscopic()
     torch.cuda.synchronize()
     lat.close()

@@ -1,0 +1,113 @@
+"""The row layout against the planes layout and against the FP64 oracle.
+
+Both layouts hold the same values and run the same collision; the row
+kernels address a wave's 19 sources through scalar row bases, take the full
+wall rule on rows of a y or z face and the x-face rule on the lanes of the
+x faces.  The cases put whole 64-lane waves on lattices with every wall kind
+(half-way bounce-back on each axis, the lid on +y, -x, +x and +z, periodic
+axes), forced and unforced kernels, the printed-moment form with general
+rates, the BGK comparison model, the three storage types, and block widths
+that are and are not multiples of 64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_U = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3}
+# rows vs planes after a few steps, relative to the largest stored deviation:
+# the same arithmetic on the same inputs (the bound only allows for the
+# compiler contracting a product differently in the two kernels)
+TOL_SAME = {"f64": 1e-13, "f32": 2e-6, "f16": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def clbm():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1908_05396_amd import clbm as c
+    c.load()
+    return c
+
+
+def _geometries():
+    base = W.cavity(64, 0.05, 0.8, 200.0)
+    omegas = dict(omega_bulk=1.15, omega_high=(1.2, 1.1, 1.3, 0.95, 0.9, 1.05, 1.1, 1.2, 0.85))
+    return {
+        "lid_py_130x12x9": base.with_(nx=130, ny=12, nz=9, name="rows_py"),
+        "lid_mx_64x10x7": base.with_(nx=64, ny=10, nz=7, lid_face=W.LID_MX, lid_velocity=(0.0, 0.05, 0.01)),
+        "lid_px_96x9x8": base.with_(nx=96, ny=9, nz=8, lid_face=W.LID_PX, lid_velocity=(0.0, -0.03, 0.02)),
+        "lid_pz_70x8x11": base.with_(nx=70, ny=8, nz=11, lid_face=W.LID_PZ, lid_velocity=(0.05, -0.02, 0.0)),
+        "periodic_xz_lid_128x10x6": base.with_(nx=128, ny=10, nz=6, periodic=(1, 0, 1)),
+        "periodic_box_64x5x6": W.LatticeSpec(nx=64, ny=5, nz=6, K=0.02, n=0.9, periodic=(1, 1, 1), name="box"),
+        "channel_forced_64x16x4": W.poiseuille(64, 16, 4, n=0.6, Re=5.0, umax=0.02),
+        "ghat_general_80x9x7": base.with_(nx=80, ny=9, nz=7, **omegas),
+        "srt_72x9x8": base.with_(nx=72, ny=9, nz=8, model="srt"),
+    }
+
+
+def _run(clbm, spec, storage, layout, steps, seed, eps, block=None):
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout, block=block)
+    lat.init_populations(W.perturbed_populations(spec, seed, eps, device="cuda"))
+    lat.step(steps)
+    st = lat.state_view().to(torch.float64).cpu().numpy()
+    _, u = lat.macroscopic()
+    u = u.cpu().numpy()
+    f = lat.populations().cpu().numpy()
+    lat.close()
+    return st, u, f
+
+
+@pytest.mark.parametrize("geom", list(_geometries()))
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_rows_match_planes_and_oracle(clbm, geom, storage):
+    spec = _geometries()[geom]
+    steps, seed, eps = 6, 31, 1e-2
+    print(f"[gpu] layouts {geom} {storage} steps={steps}", flush=True)
+    st_r, u_r, f_r = _run(clbm, spec, storage, "rows", steps, seed, eps)
+    st_p, u_p, f_p = _run(clbm, spec, storage, "planes", steps, seed, eps)
+    same = np.abs(st_r - st_p).max()
+    print(f"    rows vs planes: max |d| diff {same:.3e} (bitwise equal: {np.array_equal(st_r, st_p)})")
+    assert same <= TOL_SAME[storage] * np.abs(st_p).max()
+    assert np.abs(f_r - f_p).max() <= TOL_SAME[storage] * np.abs(st_p).max()
+    f_ref = oracle.run(spec, W.perturbed_populations(spec, seed, eps).numpy(), steps)
+    _, u_ref = oracle.macroscopic(spec, f_ref)
+    err = np.abs(u_r - u_ref).max() / np.abs(u_ref).max()
+    print(f"    rows u vs oracle {err:.3e}")
+    if spec.force[0] != 0.0 and storage == "f16":
+        return      # the channel's body force lies below the FP16 resolution of the deviations
+    assert err < TOL_U[storage]
+
+
+@pytest.mark.parametrize("block", [(64, 1), (128, 1), (64, 4), (192, 2), (32, 4), (100, 1)])
+def test_row_block_shapes(clbm, block):
+    """Fast (width a multiple of 64) and full-rule kernels give the same bits."""
+    spec = _geometries()["lid_py_130x12x9"]
+    print(f"[gpu] rows block {block}", flush=True)
+    st, u, _ = _run(clbm, spec, "f32", "rows", 5, 8, 1e-2, block=block)
+    ref, u_ref, _ = _run(clbm, spec, "f32", "rows", 5, 8, 1e-2, block=(256, 1))
+    assert np.array_equal(st, ref) and np.array_equal(u, u_ref)
+
+
+def test_rows_rest_state_and_reductions(clbm):
+    """Rest initial state in the row layout: mass N, zero momentum, and a lid
+    that starts the flow; reductions read the row layout."""
+    spec = W.cavity(64, 0.05, 0.7, 100.0).with_(ny=20, nz=12)
+    lat = clbm.Lattice(spec, storage="f64", layout="rows")
+    lat.init_rest()
+    r0 = lat.reduce()
+    assert abs(r0["mass"] - spec.nodes) < 1e-12 * spec.nodes and r0["umax"] < 1e-15
+    lat.step(50)
+    r1 = lat.reduce()
+    two = clbm.Lattice(spec, storage="f64", layout="planes")
+    two.init_rest()
+    two.step(50)
+    r2 = two.reduce()
+    lat.close()
+    two.close()
+    assert abs(r1["mass"] - spec.nodes) < 1e-11 * spec.nodes
+    for k in ("mass", "momentum_x", "momentum_y", "momentum_z", "umax", "kinetic"):
+        assert abs(r1[k] - r2[k]) <= 1e-12 * max(1.0, abs(r2[k])), k

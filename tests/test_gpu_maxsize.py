@@ -39,22 +39,32 @@ def _oracle_rest(spec, pt, k):
     return ft[:, pt[2] - lo[2], pt[1] - lo[1], pt[0] - lo[0]]
 
 
-@pytest.mark.parametrize("storage,dims", [("f32", (1024, 1024, 1023)), ("f16", (2048, 1024, 1023))])
-def test_largest_lattice(clbm, storage, dims):
+@pytest.mark.parametrize("storage,dims,layout", [("f32", (1024, 1024, 1023), "planes"),
+                                                  ("f16", (2048, 1024, 1023), "planes"),
+                                                  ("f16", (2048, 1024, 1023), "rows")])
+def test_largest_lattice(clbm, storage, dims, layout):
+    """Planes: the largest lattices whose planes fit the 4 GiB range of a
+    buffer descriptor (one more z layer is refused).  Rows: node indices are
+    32-bit, and the FP16 lattice of just under 2^31 nodes runs in either
+    layout."""
     nx, ny, nz = dims
     spec = W.cavity(16, 0.05, 0.8, 100.0).with_(nx=nx, ny=ny, nz=nz, name=f"max_{storage}")
-    plane, nbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage))
+    plane, nbytes = clbm.buffer_size(clbm.params_from_spec(spec, storage, layout=layout))
     esize = 4 if storage == "f32" else 2
-    assert spec.nodes * esize <= (1 << 32) - 256 < (spec.nodes + nx * ny) * esize
-    print(f"[gpu] max-size {storage} {nx}x{ny}x{nz}: {spec.nodes} nodes, 2 x {nbytes / 1e9:.1f} GB", flush=True)
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False)
+    if layout == "planes":
+        assert spec.nodes * esize <= (1 << 32) - 256 < (spec.nodes + nx * ny) * esize
+    else:
+        assert spec.nodes < (1 << 31) <= spec.nodes + nx * ny
+    print(f"[gpu] max-size {storage} {layout} {nx}x{ny}x{nz}: {spec.nodes} nodes, 2 x {nbytes / 1e9:.1f} GB",
+          flush=True)
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
     lat.init_rest()
     lat.step(K_STEPS)
     pts = [(nx - 1, ny - 1, nz - 1), (0, ny - 1, nz - 1), (nx - 1, ny - 1, 0), (nx // 2, ny - 1, nz // 2),
            (nx - 2, ny - 3, nz - 2), (nx // 3, ny - 5, nz - 1), (nx - 1, ny // 2, nz - 1)]
-    st = lat.state_tensor()
-    idx = torch.tensor([(p[2] * ny + p[1]) * nx + p[0] for p in pts], device="cuda")
-    d = st[:, idx].to(torch.float64).cpu().numpy().T            # (samples, 19) deviations
+    st = lat.state_view()
+    idx = torch.tensor([(p[2], p[1], p[0]) for p in pts], device="cuda")
+    d = st[:, idx[:, 0], idx[:, 1], idx[:, 2]].to(torch.float64).cpu().numpy().T   # (samples, 19) deviations
     rest = lat.reduce()
     lat.close()
     del lat, st

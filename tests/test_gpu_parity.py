@@ -40,10 +40,10 @@ def _oracle_u(spec, seed, eps, steps):
     return rho, u
 
 
-def _gpu_run(clbm, spec, storage, seed, eps, steps, block=None):
-    print(f"[gpu] {spec.name} {spec.nx}x{spec.ny}x{spec.nz} storage={storage} seed={seed} "
+def _gpu_run(clbm, spec, storage, seed, eps, steps, block=None, layout="rows"):
+    print(f"[gpu] {spec.name} {spec.nx}x{spec.ny}x{spec.nz} storage={storage} layout={layout} seed={seed} "
           f"steps={steps} block={block}", flush=True)
-    lat = clbm.Lattice(spec, storage=storage, block=block)
+    lat = clbm.Lattice(spec, storage=storage, block=block, layout=layout)
     if seed is None:
         lat.init_rest()
     else:
@@ -77,30 +77,33 @@ def test_single_collision_populations(clbm, storage, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("layout", ["rows", "planes"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_poiseuille_config(clbm, storage):
+def test_poiseuille_config(clbm, storage, layout):
     """8x32x8 power-law channel (n = 0.5, Re = 10, u_max = 0.01, body force),
     2000 steps from rest.  FP16-deviation storage is not used here: the force
     changes the populations by ~1e-7 per step, about two FP16 ulps of the
     stored deviations, so FP16 storage cannot carry this slow acceleration."""
     spec = W.config_poiseuille()
     rho_ref, u_ref = _oracle_u(spec, None, 0.0, 2000)
-    rho, u, _ = _gpu_run(clbm, spec, storage, None, 0.0, 2000)
+    rho, u, _ = _gpu_run(clbm, spec, storage, None, 0.0, 2000, layout=layout)
     err = _normwise(u, u_ref)
-    print(f"poiseuille {storage}: {err:.3e}")
+    print(f"poiseuille {storage} {layout}: {err:.3e}")
     assert err < TOL_U[storage]
 
 
+@pytest.mark.parametrize("layout", ["rows", "planes"])
 @pytest.mark.parametrize("n", [0.5, 1.0, 1.5])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_cavity16_power_law(clbm, n, storage):
+def test_cavity16_power_law(clbm, n, storage, layout):
     """16^3 lid-driven cavity, U = 0.05, Re = 100, perturbed start (seed 1234,
-    eps 1e-3), 300 steps."""
+    eps 1e-3), 300 steps (16 nodes along x: every lane takes the full wall
+    rule in the row layout)."""
     spec = W.cavity(16, 0.05, n, 100.0, name=f"cavity16_n{n}")
     rho_ref, u_ref = _oracle_u(spec, 1234, 1e-3, 300)
-    rho, u, _ = _gpu_run(clbm, spec, storage, 1234, 1e-3, 300)
+    rho, u, _ = _gpu_run(clbm, spec, storage, 1234, 1e-3, 300, layout=layout)
     err = _normwise(u, u_ref)
-    print(f"cavity16 n={n} {storage}: {err:.3e}")
+    print(f"cavity16 n={n} {storage} {layout}: {err:.3e}")
     if storage != "f16":
         assert err < TOL_U[storage]
         return
@@ -117,33 +120,40 @@ def test_cavity16_power_law(clbm, n, storage):
     assert err < 2e-2
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_ragged_lattice(clbm, storage):
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_ragged_lattice(clbm, storage, layout):
     """70 x 20 x 9 cavity: two 64-wide tiles along x with a ragged tail of 6,
     odd y and z extents."""
     spec = W.cavity(20, 0.05, 0.8, 50.0).with_(nx=70, ny=20, nz=9, name="cavity70x20x9")
     rho_ref, u_ref = _oracle_u(spec, 99, 1e-3, 80)
-    rho, u, _ = _gpu_run(clbm, spec, storage, 99, 1e-3, 80)
+    rho, u, _ = _gpu_run(clbm, spec, storage, 99, 1e-3, 80, layout=layout)
     err = _normwise(u, u_ref)
-    print(f"ragged {storage}: {err:.3e}")
+    print(f"ragged {storage} {layout}: {err:.3e}")
     assert err < TOL_U[storage]
 
 
-def test_periodic_mixed_walls(clbm):
-    """Periodic along x and z with walls at y, a lid at -z would be invalid;
-    here a duct periodic along x with walls in y and z and a lid on +z."""
-    spec = W.LatticeSpec(nx=12, ny=10, nz=8, K=0.02, n=1.3, periodic=(1, 0, 0), lid_face=W.LID_PZ,
-                         lid_velocity=(0.03, 0.01, 0.0), name="duct_lidz")
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+@pytest.mark.parametrize("nx", [12, 64])
+def test_periodic_mixed_walls(clbm, nx, layout):
+    """A duct periodic along x with walls in y and z and a lid on +z (a lid on
+    a periodic axis would be invalid).  nx = 64: whole waves, so the row
+    layout takes its fast kernel with the periodic x-face rule."""
+    spec = W.LatticeSpec(nx=nx, ny=10, nz=8, K=0.02, n=1.3, periodic=(1, 0, 0), lid_face=W.LID_PZ,
+                         lid_velocity=(0.03, 0.01, 0.0), name=f"duct_lidz_{nx}")
     rho_ref, u_ref = _oracle_u(spec, 5, 1e-3, 150)
-    rho, u, _ = _gpu_run(clbm, spec, "f64", 5, 1e-3, 150)
+    rho, u, _ = _gpu_run(clbm, spec, "f64", 5, 1e-3, 150, layout=layout)
     assert _normwise(u, u_ref) < TOL_U["f64"]
 
 
-def test_block_shape_does_not_change_results(clbm):
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_block_shape_does_not_change_results(clbm, layout):
+    """Row layout: widths that are multiples of 64 take the fast kernel, the
+    others the full-rule kernel; both give the same bits."""
     spec = W.cavity(20, 0.05, 0.7, 100.0).with_(nx=96, name="cavity96x20x20")
     results = []
     for block in [(64, 1), (64, 4), (32, 2), (128, 2), (96, 2)]:
-        _, u, _ = _gpu_run(clbm, spec, "f32", 4, 1e-3, 30, block=block)
+        _, u, _ = _gpu_run(clbm, spec, "f32", 4, 1e-3, 30, block=block, layout=layout)
         results.append(u)
     for u in results[1:]:
         assert np.array_equal(u, results[0])
