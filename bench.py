@@ -3,16 +3,19 @@
 
 Workload (default): lid-driven cubic cavity 512^3 (134.2 M nodes), Re = 3200,
 n = 0.75, lid velocity 0.04, rest start, 5000 steps; FP32 storage of f - w
-with FP32 arithmetic; the FP64 mass reduction every 100 steps tracks the mass
-drift.  One step = one fused pull stream-collide launch over the whole lattice.
+with FP32 arithmetic, row-interleaved state layout; the FP64 mass reduction
+every 100 steps tracks the mass drift.  One step = the fused pull
+stream-collide over the whole lattice: one launch for the rows off the y and
+z faces and one for the face rows (about 0.8% of the nodes at 512^3).
 The FP16-deviation and FP64 storage runs of the same workload end at the same
 step, and the errors of FP32 and FP16 against FP64 are reported on the
 centrelines u_x(y), u_y(x) and normwise over the whole field.
 
 Prints ONE JSON line: MLUPS of the timed region (exactly --steps steps after
 --warmup untimed ones, bracketed by device synchronisation), the roofline of
-the stream-collide kernel (algorithmic bytes per launch / average launch time
-measured with events on the launch stream), the FP16-deviation and FP64
+the stream-collide step (algorithmic bytes per step / average step time
+measured with events on the launch stream, both launches of a step between
+the events), the planes layout and the two-step launch form, the FP16-deviation and FP64
 storage variants of the same workload, the 64-cavity batch (persistent
 graph-replayed launch vs one launch per instance), the achievable copy
 bandwidth, and the CPU oracle timed on the host cores on a bounded sample of
@@ -58,7 +61,7 @@ def measured_traffic(storage: str, workload: str, kernel: str):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_(?:launch|step):\s*([0-9.eE+]+)", text)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_bytes.group(1))
@@ -303,6 +306,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=512, help="cavity edge length")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--layout", default="rows", choices=["rows", "planes"],
+                    help="state layout of the main run and the storage variants")
     ap.add_argument("--reduce-every", type=int, default=100)
     ap.add_argument("--variant-steps", type=int, default=-1,
                     help="steps of the other storage variants (default: --steps + --warmup - 20, so that "
@@ -313,6 +318,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other launch form, the planes layout, the BGK comparison and the one-buffer "
+                         "form (short runs under a profiler)")
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--stability", action="store_true",
                     help="instead of the benchmark: largest stable lid velocity of the 64^3 cavity, cascaded "
@@ -348,7 +356,7 @@ def main():
     compare = not args.no_variants and args.variant_steps < 0
     vsteps = args.steps + args.warmup - args.variant_warmup if args.variant_steps < 0 else args.variant_steps
     main_run = time_lattice(clbm, torch, spec, args.storage, args.steps, args.warmup, args.reduce_every,
-                            keep_u=compare)
+                            keep_u=compare, layout=args.layout)
     mlups = spec.nodes * args.steps / (main_run["ms_per_step"] * args.steps * 1e-3) / 1e6
 
     variants = {}
@@ -357,7 +365,8 @@ def main():
         for st in ("f16", "f64", "f32"):
             if st == args.storage:
                 continue
-            r = time_lattice(clbm, torch, spec, st, vsteps, args.variant_warmup, args.reduce_every, keep_u=compare)
+            r = time_lattice(clbm, torch, spec, st, vsteps, args.variant_warmup, args.reduce_every, keep_u=compare,
+                             layout=args.layout)
             fields[st] = r.pop("u", None)
             spl = r["launch"]["fuse_steps"]
             variants[st] = {
@@ -369,7 +378,7 @@ def main():
             }
     # the other launch form of each storage (one vs two steps per launch)
     launch_forms = {}
-    if not args.no_variants:
+    if not (args.no_variants or args.no_extras):
         for st in ("f32", "f64", "f16"):
             r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, launch=OTHER_FORM)
             spl = r["launch"]["fuse_steps"]
@@ -382,7 +391,7 @@ def main():
 
     # the planes layout, one step per launch, for each storage
     planes_layout = {}
-    if not args.no_variants:
+    if not (args.no_variants or args.no_extras):
         for st in ("f32", "f16", "f64"):
             r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, layout="planes")
             planes_layout[st] = {
@@ -393,7 +402,7 @@ def main():
 
     # the single-relaxation-time comparison model on the same workload (FP32)
     comparison = None
-    if not args.no_variants:
+    if not (args.no_variants or args.no_extras):
         r = time_lattice(clbm, torch, spec.with_(model="srt"), "f32", 300, 20, args.reduce_every)
         comparison = {"model": "single-relaxation-time (BGK), same power law, FP32, 300 steps",
                       "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
@@ -403,7 +412,7 @@ def main():
 
     # one state buffer, stepped in place (AA pattern), FP32
     in_place = None
-    if not args.no_variants:
+    if not (args.no_variants or args.no_extras):
         r = time_lattice(clbm, torch, spec, "f32", 300, 20, args.reduce_every, in_place=True)
         in_place = {"storage": "f32", "steps": 300, "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
                     "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
