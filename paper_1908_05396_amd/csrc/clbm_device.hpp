@@ -262,10 +262,10 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
         for (int it = 0; it < NewtonTol<float>::maxit; ++it) {
             const float e = fast_exp2(sf);
             const float it1 = fast_rcp(0.5f + e);
-            const float q = af * (it1 * it1) + bf;
+            const float u = af * (it1 * it1);
+            const float q = u + bf;
             const float phi = sf - cf - kf * fast_log2(q);
-            const float dphi = 1.0f + two_kf * (1.0f - bf * fast_rcp(q)) * (e * it1);
-            sf = clampv(sf - phi * fast_rcp(dphi), lo, hi);
+            sf = clampv(sf - phi * q * fast_rcp(q + two_kf * u * (e * it1)), lo, hi);
         }
         s = (T)sf;
         if (!(s == s)) s = clampv(c + p.k * fast_log2(q0), p.s_lo, p.s_hi);   // FP32 range trouble
@@ -274,11 +274,13 @@ __device__ inline T solve_tau(const Relax<T> &p, T rho, T a, T b) {
     for (int it = 0; it < (NewtonTol<T>::fixed ? NI : NewtonTol<T>::maxit); ++it) {
         const T e = fast_exp2(s);                 // tau - 1/2
         const T it1 = fast_rcp(T(0.5) + e);       // 1/tau
-        const T q = a * (it1 * it1) + b;
+        const T u = a * (it1 * it1);              // a / tau^2
+        const T q = u + b;
         const T phi = s - c - p.k * fast_log2(q);
-        // slope 1 + 2k (a / (tau^2 q)) (tau - 1/2) / tau, with a/(tau^2 q) = 1 - b/q
-        const T dphi = T(1) + two_k * (T(1) - b * fast_rcp(q)) * (e * it1);
-        const T sn = clampv(s - phi * fast_rcp(dphi), p.s_lo, p.s_hi);
+        // slope 1 + 2k (u/q) (tau - 1/2)/tau = (q + 2k u (tau - 1/2)/tau) / q, so the
+        // Newton step phi/slope takes one reciprocal; the denominator is at
+        // least (1 - |2k|) q > 0 for n in (0, 2) and at least q for n >= 1
+        const T sn = clampv(s - phi * q * fast_rcp(q + two_k * u * (e * it1)), p.s_lo, p.s_hi);
         if (NewtonTol<T>::fixed) {
             s = sn;
             continue;
