@@ -90,8 +90,7 @@ typedef enum {
  * and give the same results; the row layout keeps the 19 populations of a row
  * within 19*nx consecutive values, so one step reads 9 and writes 1 compact
  * region per row instead of touching 38 planes far apart in memory, which
- * DRAM serves faster.  The one-buffer form, two steps per launch and batches
- * need planes. */
+ * DRAM serves faster.  Two steps per launch and batches need planes. */
 typedef enum {
     CLBM_LAYOUT_PLANES = 0,
     CLBM_LAYOUT_ROWS = 1
@@ -167,8 +166,7 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
  * (time t, before its collision), so clbm_populations returns those;
  * clbm_init_* store the initial populations without colliding them;
  * clbm_step accepts even step counts only (EINVAL otherwise); one step per
- * launch (fuse_steps = 2 is refused); the planes layout only (EINVAL for
- * rows).  Velocities from clbm_macroscopic and
+ * launch (fuse_steps = 2 is refused); either layout.  Velocities from clbm_macroscopic and
  * clbm_reduce are the same physical quantities as in the two-buffer form. */
 clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out);
 

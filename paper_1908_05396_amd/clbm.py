@@ -201,15 +201,15 @@ class Lattice:
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
                  block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto",
                  in_place: bool = False, layout: str = None):
-        """layout: "rows" or "planes"; None picks planes for the one-buffer
-        form and for two steps per launch (which need them), rows otherwise."""
+        """layout: "rows" or "planes"; None picks planes for two steps per
+        launch (which need them), rows otherwise."""
         lib = load()
         self.spec = spec
         self.storage = storage
         self.in_place = bool(in_place)
         if layout is None:
             two_step = bool(launch) and int(launch.get("fuse_steps", 1)) == 2
-            layout = "planes" if (self.in_place or two_step) else "rows"
+            layout = "planes" if two_step else "rows"
         self.layout = layout
         self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision, layout)
         self.plane, self.nbytes = buffer_size(self.params)

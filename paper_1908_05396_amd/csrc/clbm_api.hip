@@ -116,8 +116,6 @@ static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b,
     clbm_buffer_size(p, nullptr, &need);
     if (!pop_a || !pop_b) return fail(CLBM_EINVAL, "state buffers must not be NULL");
     if (pop_a == pop_b && !in_place) return fail(CLBM_EINVAL, "the two state buffers must differ");
-    if (in_place && p->layout != CLBM_LAYOUT_PLANES)
-        return fail(CLBM_EINVAL, "the one-buffer form uses the planes layout");
     if (!aligned256(pop_a) || !aligned256(pop_b)) return fail(CLBM_EINVAL, "state buffers must be 256-byte aligned");
     if (bytes_each < need)
         return fail(CLBM_EINVAL, "state buffers hold %zu bytes, need %zu", bytes_each, need);

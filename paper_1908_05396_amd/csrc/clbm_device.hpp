@@ -151,30 +151,35 @@ template <typename S, int G> struct PlaneGroup {
     }
 };
 
+// Raw buffer access at a lane byte offset `byte` plus a uniform byte offset
+// `so` (the instruction's scalar offset operand).  Callers that pass so != 0
+// keep byte + so inside the descriptor's range, so the result does not
+// depend on whether the range check counts the scalar offset.
 template <typename S> struct RawBits;
 template <> struct RawBits<float> {
-    template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte, 0, Aux));
+    template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte, uint32_t so = 0) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte, (int)so, Aux));
     }
-    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte, 0, Aux);
+    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v, uint32_t so = 0) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)byte, (int)so, Aux);
     }
 };
 template <> struct RawBits<__half> {
-    template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte) {
-        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte, 0, Aux)));
+    template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte, uint32_t so = 0) {
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte, (int)so, Aux)));
     }
-    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, __float2half_rn(v)), r, (int)byte, 0, Aux);
+    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v, uint32_t so = 0) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, __float2half_rn(v)), r, (int)byte, (int)so,
+                                              Aux);
     }
 };
 template <> struct RawBits<double> {
-    template <int Aux> __device__ static double load(__amdgpu_buffer_rsrc_t r, uint32_t byte) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte, 0, Aux));
+    template <int Aux> __device__ static double load(__amdgpu_buffer_rsrc_t r, uint32_t byte, uint32_t so = 0) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte, (int)so, Aux));
     }
-    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, double v) {
+    template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, double v, uint32_t so = 0) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte, 0, Aux);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte, (int)so, Aux);
     }
 };
 

@@ -22,7 +22,7 @@
 //                             low enough for eight waves per SIMD.
 //   stream_collide_any        any block shape: the full rule on every lane
 //                             (narrow lattices).
-#include "clbm_internal.hpp"
+#include "clbm_rows.hpp"
 
 namespace clbm {
 
@@ -41,10 +41,6 @@ __device__ inline T pull_any(const S *__restrict__ A, const Geom &g, const Relax
     if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
     if (!wall) return (T)Conv<S, T>::load(A[elem(g, a, sx, sy, sz)]);
     return wall_value<T>((T)Conv<S, T>::load(A[elem(g, opp(a), x, y, z)]), p, a, in_lid);
-}
-
-__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
 }
 
 __device__ inline void tile_of(const LaunchGrid &L, uint32_t &tx, uint32_t &ty, int &z) {
@@ -135,33 +131,14 @@ __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, cons
         RawBits<S>::template store<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a]);
 }
 
-struct RowGrid {
-    uint32_t gx;            // tiles along x
-    uint32_t rows;          // rows handled by the launch
-    uint32_t aligned;       // largest multiple of 8 <= number of workgroups
-    int32_t remap;          // XCD-contiguous tile order
-    int32_t zf, yf;         // face rows: z faces (1 or 2) and y faces (1 or 2)
-};
-
-// Row index of the wave and tile of the workgroup (blockDim.x a multiple of 64).
-__device__ inline bool row_of(const RowGrid &R, int &x, uint32_t &ri) {
-    uint32_t b = blockIdx.x;
-    if (R.remap && b < R.aligned) b = (b & 7u) * (R.aligned >> 3) + (b >> 3);
-    const uint32_t tx = b % R.gx;
-    ri = __builtin_amdgcn_readfirstlane((b / R.gx) * blockDim.y + threadIdx.y);
-    x = (int)(tx * blockDim.x + threadIdx.x);
-    return ri < R.rows;
-}
-
 template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 stream_collide_rows_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, RowGrid R) {
     int x;
     uint32_t ri;
     if (!row_of(R, x, ri) || x >= g.nx) return;
-    // inner rows: y in [1, ny - 2], z in [1, nz - 2]
-    const uint32_t w = (uint32_t)g.ny - 2u;
-    const int y = 1 + (int)(ri % w), z = 1 + (int)(ri / w);
+    int y, z;
+    inner_row(g, ri, y, z);
     row_step<S, T, Forced, LdAux, StAux, Route, false>(A, B, g, p, x, y, z);
 }
 
@@ -171,17 +148,8 @@ stream_collide_rows_face_kernel(const S *__restrict__ A, S *__restrict__ B, Geom
     int x;
     uint32_t ri;
     if (!row_of(R, x, ri) || x >= g.nx) return;
-    // every row of the z faces, then the y-face rows of the inner z layers
     int y, z;
-    const uint32_t nzr = (uint32_t)R.zf * (uint32_t)g.ny;
-    if (ri < nzr) {
-        y = (int)(ri % (uint32_t)g.ny);
-        z = ri < (uint32_t)g.ny ? 0 : g.nz - 1;
-    } else {
-        const uint32_t k = ri - nzr;
-        z = 1 + (int)(k / (uint32_t)R.yf);
-        y = (k % (uint32_t)R.yf) == 0 ? 0 : g.ny - 1;
-    }
+    face_row(g, R, ri, y, z);
     row_step<S, T, Forced, LdAux, StAux, Route, true>(A, B, g, p, x, y, z);
 }
 
@@ -206,28 +174,16 @@ template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
 static hipError_t launch_rows_k(const S *a, S *b, const Geom &g, const Relax<T> &p, const StepLaunch &c,
                                 hipStream_t st) {
     // inner rows, then the face rows
-    RowGrid R;
-    R.gx = (g.nx + c.bx - 1) / c.bx;
-    R.remap = c.xcd_remap;
-    R.zf = g.nz > 1 ? 2 : 1;
-    R.yf = g.ny > 1 ? 2 : 1;
+    const RowLaunch L = row_launch(g, c.bx, c.by, c.xcd_remap);
     const dim3 block(c.bx, c.by);
-    const uint32_t inner = (g.ny > 2 && g.nz > 2) ? (uint32_t)(g.ny - 2) * (uint32_t)(g.nz - 2) : 0u;
-    if (inner > 0) {
-        R.rows = inner;
-        const uint32_t nb = R.gx * ((inner + c.by - 1) / c.by);
-        R.aligned = nb & ~7u;
-        hipLaunchKernelGGL((stream_collide_rows_kernel<S, T, Forced, LdAux, StAux, Route>), dim3(nb), block, 0, st,
-                           a, b, g, p, R);
+    if (L.inner.rows > 0) {
+        hipLaunchKernelGGL((stream_collide_rows_kernel<S, T, Forced, LdAux, StAux, Route>), dim3(L.inner_blocks),
+                           block, 0, st, a, b, g, p, L.inner);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    R.rows = (uint32_t)R.zf * (uint32_t)g.ny + (g.nz > 2 ? (uint32_t)(g.nz - 2) * (uint32_t)R.yf : 0u);
-    const uint32_t nb = R.gx * ((R.rows + c.by - 1) / c.by);
-    R.aligned = nb & ~7u;
-    R.remap = 0;
-    hipLaunchKernelGGL((stream_collide_rows_face_kernel<S, T, Forced, LdAux, StAux, Route>), dim3(nb), block, 0, st,
-                       a, b, g, p, R);
+    hipLaunchKernelGGL((stream_collide_rows_face_kernel<S, T, Forced, LdAux, StAux, Route>), dim3(L.face_blocks),
+                       block, 0, st, a, b, g, p, L.face);
     return hipGetLastError();
 }
 

@@ -148,15 +148,16 @@ def test_srt_model_restrictions(clbm):
     assert clbm.load().clbm_batch_size(arr, 1, ctypes.byref(n)) == clbm.CLBM_EINVAL
 
 
-def test_row_layout_restrictions(clbm):
-    """The one-buffer form needs the planes layout; the check comes before any
-    device call."""
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_in_place_create_checks_buffer_first(clbm, layout):
+    """The one-buffer form takes either layout; a misaligned buffer is refused
+    before any device call."""
     lib = clbm.load()
     h = ctypes.c_void_p()
-    p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32", layout="rows")
-    assert lib.clbm_create_in_place(ctypes.byref(p), ctypes.c_void_p(0x1000), ctypes.c_size_t(1 << 30),
+    p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32", layout=layout)
+    assert lib.clbm_create_in_place(ctypes.byref(p), ctypes.c_void_p(0x1004), ctypes.c_size_t(1 << 30),
                                     ctypes.byref(h)) == clbm.CLBM_EINVAL
-    assert "planes layout" in lib.clbm_last_error().decode()
+    assert "aligned" in lib.clbm_last_error().decode()
 
 
 def test_size_limits_per_layout(clbm):

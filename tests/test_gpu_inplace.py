@@ -7,8 +7,9 @@ element; velocities are compared with the two-buffer form (whose buffer holds
 the post-collision state of the same time).  The cases cover every wall kind
 (half-way bounce-back on each axis, the lid on +y, -x and +z, periodic axes),
 the forced kernel, the printed-moment collision form, the BGK comparison
-model, the three storage types, and the 512^3 benchmark lattice by light
-cone.
+model, the three storage types, both state layouts (narrow lattices take the
+full-rule kernels, lattices of whole 64-lane waves the row kernels with scalar
+row bases), and the 512^3 benchmark lattice by light cone.
 """
 import numpy as np
 import pytest
@@ -20,10 +21,11 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL_U = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3}
-# element-wise bounds on populations after a few steps: FP64 rounding of the
-# oracle's full populations, FP32 ~16 ulp of the largest population, FP16
-# the rounding of deviations of size ~1e-2
-TOL_F = {"f64": 2e-15, "f32": 1e-6, "f16": 3e-5}
+# element-wise bounds on populations after a few steps: FP64 rounding of
+# populations of size ~1/3 (ulp 5.6e-17) over 8 steps, up to ~70 ulp; FP32
+# ~16 ulp of the largest population; FP16 the rounding of deviations of size
+# ~1e-2
+TOL_F = {"f64": 4e-15, "f32": 1e-6, "f16": 3e-5}
 
 
 @pytest.fixture(scope="module")
@@ -45,20 +47,31 @@ def _geometries():
         "channel_1xNx1": W.poiseuille(1, 12, 1, n=0.6, Re=5.0, umax=0.02),
         "periodic_box": W.LatticeSpec(nx=5, ny=7, nz=6, K=0.02, n=0.9, periodic=(1, 1, 1), name="box"),
         "srt_cavity": cav.with_(nx=11, ny=13, nz=10, model="srt"),
+        # whole 64-lane waves: the row-layout kernels with scalar row bases
+        "wide_lid_mx": cav.with_(nx=64, ny=10, nz=7, lid_face=W.LID_MX, lid_velocity=(0.0, 0.05, 0.01)),
+        "wide_lid_px": cav.with_(nx=96, ny=9, nz=8, lid_face=W.LID_PX, lid_velocity=(0.0, -0.03, 0.02)),
+        "wide_lid_pz": cav.with_(nx=70, ny=8, nz=11, lid_face=W.LID_PZ, lid_velocity=(0.05, -0.02, 0.0)),
+        "wide_periodic_xz_lid": cav.with_(nx=128, ny=10, nz=6, periodic=(1, 0, 1)),
+        "wide_periodic_y": cav.with_(nx=64, ny=9, nz=7, periodic=(0, 1, 0), lid_face=W.LID_PZ,
+                                     lid_velocity=(0.04, 0.01, 0.0)),
+        "wide_box": W.LatticeSpec(nx=64, ny=5, nz=6, K=0.02, n=0.9, periodic=(1, 1, 1), name="wide_box"),
+        "wide_forced": W.poiseuille(64, 16, 4, n=0.6, Re=5.0, umax=0.02),
+        "wide_srt": cav.with_(nx=72, ny=9, nz=8, model="srt"),
     }
 
 
+@pytest.mark.parametrize("layout", ["rows", "planes"])
 @pytest.mark.parametrize("geom", list(_geometries()))
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_in_place_matches_oracle_and_two_buffer_form(clbm, geom, storage):
+def test_in_place_matches_oracle_and_two_buffer_form(clbm, geom, storage, layout):
     spec = _geometries()[geom]
     steps, seed, eps = 8, 21, 1e-2
-    print(f"[gpu] in-place {geom} {spec.nx}x{spec.ny}x{spec.nz} {storage} steps={steps}", flush=True)
+    print(f"[gpu] in-place {geom} {spec.nx}x{spec.ny}x{spec.nz} {storage} {layout} steps={steps}", flush=True)
     f0 = W.perturbed_populations(spec, seed, eps)
     f_ref = oracle.run(spec, f0.numpy(), steps)
     _, u_ref = oracle.macroscopic(spec, f_ref)
 
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False, in_place=True)
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, in_place=True, layout=layout)
     lat.init_populations(f0.to("cuda"))
     lat.step(steps)
     f_gpu = lat.populations().cpu().numpy()
@@ -66,7 +79,7 @@ def test_in_place_matches_oracle_and_two_buffer_form(clbm, geom, storage):
     u_in = u_in.cpu().numpy()
     lat.close()
 
-    two = clbm.Lattice(spec, storage=storage, track_residual=False)
+    two = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
     two.init_populations(f0.to("cuda"))
     two.step(steps)
     _, u_two = two.macroscopic()
@@ -102,13 +115,14 @@ def test_in_place_rules(clbm):
     lat.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
-def test_in_place_full_size_light_cone(clbm, storage):
+@pytest.mark.parametrize("storage,layout", [("f32", "rows"), ("f64", "rows"), ("f16", "rows"), ("f32", "planes")])
+def test_in_place_full_size_light_cone(clbm, storage, layout):
     """512^3 cavity (the benchmark lattice) in place for 6 steps from a
     perturbed start; sampled nodes against the oracle on (2k+1)^3 sub-boxes."""
     spec = W.config_cavity512()
     k, seed, eps = 6, 77, 2e-3
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False, in_place=True)
+    print(f"[gpu] in-place full size {storage} {layout}", flush=True)
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, in_place=True, layout=layout)
     f0 = W.perturbed_populations(spec, seed, eps, device="cuda")
     lat.init_populations(f0)
     del f0
@@ -117,9 +131,9 @@ def test_in_place_full_size_light_cone(clbm, storage):
     nx, ny, nz = spec.nx, spec.ny, spec.nz
     pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx // 2, ny - 1, nz // 2), (1, ny // 3, nz - 1),
            (nx - 1, 0, nz // 4), (nx // 2, ny // 2, nz // 2)]
-    st = lat.state_tensor()
-    idx = torch.tensor([(p[2] * ny + p[1]) * nx + p[0] for p in pts], device="cuda")
-    d = st[:, idx].to(torch.float64).cpu().numpy().T
+    st = lat.state_view()
+    idx = torch.tensor([(p[2], p[1], p[0]) for p in pts], device="cuda")
+    d = st[:, idx[:, 0], idx[:, 1], idx[:, 2]].to(torch.float64).cpu().numpy().T
     lat.close()
     del lat, st
     torch.cuda.empty_cache()

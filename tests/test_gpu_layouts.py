@@ -43,6 +43,8 @@ def _geometries():
         "lid_pz_70x8x11": base.with_(nx=70, ny=8, nz=11, lid_face=W.LID_PZ, lid_velocity=(0.05, -0.02, 0.0)),
         "periodic_xz_lid_128x10x6": base.with_(nx=128, ny=10, nz=6, periodic=(1, 0, 1)),
         "periodic_box_64x5x6": W.LatticeSpec(nx=64, ny=5, nz=6, K=0.02, n=0.9, periodic=(1, 1, 1), name="box"),
+        "periodic_y_lid_pz_64x9x7": base.with_(nx=64, ny=9, nz=7, periodic=(0, 1, 0), lid_face=W.LID_PZ,
+                                               lid_velocity=(0.04, 0.01, 0.0)),
         "channel_forced_64x16x4": W.poiseuille(64, 16, 4, n=0.6, Re=5.0, umax=0.02),
         "ghat_general_80x9x7": base.with_(nx=80, ny=9, nz=7, **omegas),
         "srt_72x9x8": base.with_(nx=72, ny=9, nz=8, model="srt"),
