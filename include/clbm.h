@@ -90,7 +90,7 @@ typedef enum {
  * and give the same results; the row layout keeps the 19 populations of a row
  * within 19*nx consecutive values, so one step reads 9 and writes 1 compact
  * region per row instead of touching 38 planes far apart in memory, which
- * DRAM serves faster.  Two steps per launch and batches need planes. */
+ * DRAM serves faster.  Two steps per launch need planes. */
 typedef enum {
     CLBM_LAYOUT_PLANES = 0,
     CLBM_LAYOUT_ROWS = 1
@@ -251,16 +251,19 @@ const char *clbm_last_error(void);
  * Batches: many independent lattices (uneven sizes, Re, n, lids, forces)
  * advanced together, one persistent launch per time step whose workgroups
  * stride over the tiles of all instances; k steps are captured into a
- * hipGraph and replayed.  All instances share the storage type and use the
- * planes layout (EINVAL otherwise).  Instance i occupies 19 planes
- * (clbm_buffer_size of its params) at a 256-byte-aligned offset of each pool,
- * in instance order.
+ * hipGraph and replayed.  All instances share the storage type and the
+ * layout (EINVAL otherwise).  Instance i occupies clbm_buffer_size bytes of
+ * its params, rounded up to 256, at a 256-byte-aligned offset of each pool, in
+ * instance order.  Row layout: each wave takes (instance, row, run of 64 x)
+ * items; planes: each workgroup takes (instance, z layer, run of bx nodes)
+ * tiles.
  * ------------------------------------------------------------------------ */
 typedef struct clbm_batch clbm_batch;
 
 typedef struct {
-    int32_t bx, by;            /* tile: bx consecutive nodes of one z layer (x fastest), a multiple
-                                  of 64, <= 512 (<= 256 for FP64); by must be 1 */
+    int32_t bx, by;            /* threads per workgroup, a multiple of 64, <= 512 (<= 256 for FP64);
+                                  planes: the tile is bx consecutive nodes of one z layer (x fastest);
+                                  rows: bx / 64 waves, each on its own items; by must be 1 */
     int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu x 256 workgroups (1..64) */
     int32_t graph_steps;       /* steps per captured graph (0: plain launches) */
 } clbm_batch_config;

@@ -339,14 +339,15 @@ class Batch:
     stepped together by the batched persistent launch."""
 
     def __init__(self, specs, storage: str = "f32", device="cuda", track_residual: bool = False,
-                 tune_cache: str = None, collision: str = "auto"):
+                 tune_cache: str = None, collision: str = "auto", layout: str = "rows"):
         lib = load()
         self.specs = list(specs)
         self.storage = storage
+        self.layout = layout
         n = len(self.specs)
         arr = (Params * n)()
         for i, sp in enumerate(self.specs):
-            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision, "planes")
+            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision, layout)
         self._params = arr
         nbytes = ctypes.c_size_t()
         _check(lib.clbm_batch_size(arr, n, ctypes.byref(nbytes)))

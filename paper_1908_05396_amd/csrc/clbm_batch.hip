@@ -1,26 +1,31 @@
 // Batched stepping of many independent lattices (declared in clbm.h).
 //
 // Every instance keeps its own geometry, power-law parameters, lid and
-// force; all share the storage type.  One persistent launch per time step
-// covers the tiles of all instances: workgroup b processes tiles b, b + G,
-// b + 2G, ... of a flattened tile list, each tile being (instance, z layer,
-// run of bx consecutive nodes of that layer in x-fastest order), so small
-// lattices leave no lanes idle except at the end of a layer.  k consecutive
-// steps are captured into a hipGraph on a library stream and replayed on the
-// caller's stream.
+// force; all share the storage type and the state layout.  One persistent
+// launch per time step covers the tiles of all instances.  Planes layout:
+// workgroup b processes tiles b, b + G, b + 2G, ... of a flattened tile list,
+// each tile being (instance, z layer, run of bx consecutive nodes of that
+// layer in x-fastest order), so small lattices leave no lanes idle except at
+// the end of a layer.  Row layout: every wave takes items (instance, row, run
+// of 64 x) of a flattened list in the same strided way, so the wave's row is
+// uniform and its populations come through scalar row bases, with the face
+// rules taken per wave (rows on a y or z face) or per lane (x faces).  k
+// consecutive steps are captured into a hipGraph on a library stream and
+// replayed on the caller's stream.
 #include <algorithm>
 #include <vector>
 
 #include "clbm_host.hpp"
+#include "clbm_rows.hpp"
 
 namespace clbm {
 
 template <typename T> struct BatchInst {
     Geom g;
     Relax<T> p;
-    int64_t base;       // element offset of the instance's first plane in each pool
+    int64_t base;       // element offset of the instance's state in each pool
     uint32_t tile0;     // first tile of the instance in the flattened list
-    uint32_t chunks;    // tiles per z layer
+    uint32_t chunks;    // tiles per z layer (planes) or 64-wide runs per row (rows)
     float inv_nx;       // 1 / nx, for the row of a node within a layer
     int32_t forced;
 };
@@ -56,9 +61,51 @@ batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
     }
 }
 
+template <typename S, typename T, bool Forced, int Route>
+__device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T> &p, int x, int y, int z) {
+    if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1)
+        row_step<S, T, Forced, 0, 2, Route, true>(A, B, g, p, x, y, z);
+    else
+        row_step<S, T, Forced, 0, 2, Route, false>(A, B, g, p, x, y, z);
+}
+
+template <typename S, typename T, int Route>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
+                  const int32_t *__restrict__ tile_inst, uint32_t ntiles) {
+    const uint32_t waves = blockDim.x >> 6;
+    const uint32_t w0 = blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63u);
+    for (uint32_t t = w0; t < ntiles; t += gridDim.x * waves) {
+        const int i = __builtin_amdgcn_readfirstlane(tile_inst[t]);
+        const Geom g = inst[i].g;
+        const int64_t base = inst[i].base;
+        const uint32_t local = t - inst[i].tile0;
+        const uint32_t chunks = inst[i].chunks;
+        const uint32_t row = local / chunks;
+        const int x = (int)((local - row * chunks) * 64u) + lane;
+        const int y = (int)(row % (uint32_t)g.ny), z = (int)(row / (uint32_t)g.ny);
+        if (x >= g.nx) continue;
+        const Relax<T> &p = inst[i].p;
+        if (inst[i].forced)
+            batch_row<S, T, true, Route>(A + base, B + base, g, p, x, y, z);
+        else
+            batch_row<S, T, false, Route>(A + base, B + base, g, p, x, y, z);
+    }
+}
+
 template <typename S, typename T>
 static hipError_t launch_batch_t(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
-                                 int route, dim3 grid, dim3 block, hipStream_t st) {
+                                 int route, bool rows, dim3 grid, dim3 block, hipStream_t st) {
+    if (rows) {
+        if (route == 0)
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0>), grid, block, 0, st, (const S *)A, (S *)B,
+                               (const BatchInst<T> *)inst, tiles, ntiles);
+        else
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1>), grid, block, 0, st, (const S *)A, (S *)B,
+                               (const BatchInst<T> *)inst, tiles, ntiles);
+        return hipGetLastError();
+    }
     if (route == 0)
         hipLaunchKernelGGL((batch_step_kernel<S, T, 0>), grid, block, 0, st, (const S *)A, (S *)B,
                            (const BatchInst<T> *)inst, tiles, ntiles);
@@ -69,11 +116,11 @@ static hipError_t launch_batch_t(const void *A, void *B, const void *inst, const
 }
 
 static hipError_t launch_batch(int storage, const void *A, void *B, const void *inst, const int32_t *tiles,
-                               uint32_t ntiles, int route, dim3 grid, dim3 block, hipStream_t st) {
+                               uint32_t ntiles, int route, bool rows, dim3 grid, dim3 block, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, grid, block, st);
-    case 1: return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, grid, block, st);
-    default: return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, grid, block, st);
+    case 0: return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
+    case 1: return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
+    default: return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
     }
 }
 
@@ -91,6 +138,7 @@ struct clbm_batch {
     int count;
     int storage;
     int route;
+    bool rows;              // row layout
     std::vector<clbm_params> prm;
     std::vector<Geom> geom;
     std::vector<Relax<double>> rd;
@@ -126,8 +174,9 @@ struct clbm_batch {
 
 namespace {
 
+// each instance's state starts 256-byte aligned in the pools
 size_t instance_bytes(const clbm_params *p) {
-    return state_bytes_of(p);
+    return (state_bytes_of(p) + 255) / 256 * 256;
 }
 
 void drop_graphs(clbm_batch *b) {
@@ -162,16 +211,21 @@ clbm_status upload_tables_t(clbm_batch *b, const std::vector<Relax<T>> &relax) {
         d.g = g;
         d.p = relax[i];
         d.base = b->base[i];
-        d.chunks = (uint32_t)((g.nxy + b->cfg.bx - 1) / b->cfg.bx);
         d.inv_nx = 1.0f / (float)g.nx;
         d.tile0 = (uint32_t)total;
         d.forced = b->forced[i];
-        total += (uint64_t)d.chunks * (uint64_t)g.nz;
+        if (b->rows) {
+            d.chunks = (uint32_t)((g.nx + 63) / 64);
+            total += (uint64_t)d.chunks * (uint64_t)g.ny * (uint64_t)g.nz;
+        } else {
+            d.chunks = (uint32_t)((g.nxy + b->cfg.bx - 1) / b->cfg.bx);
+            total += (uint64_t)d.chunks * (uint64_t)g.nz;
+        }
     }
     if (total > 0x7fffffffull) return fail(CLBM_EINVAL, "batch has more than 2^31 tiles");
     tiles.resize(total);
     for (int i = 0; i < b->count; ++i) {
-        const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz;
+        const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz * (b->rows ? (uint64_t)b->geom[i].ny : 1u);
         std::fill(tiles.begin() + inst[i].tile0, tiles.begin() + inst[i].tile0 + n, i);
     }
     if (total > b->tile_cap) {
@@ -193,10 +247,12 @@ clbm_status upload_tables(clbm_batch *b) {
 }
 
 hipError_t launch_one_step(clbm_batch *b, int from, hipStream_t st) {
+    // rows: a tile is one wave's item, bx / 64 of them per workgroup
+    const uint64_t per_block = b->rows ? (uint64_t)(b->cfg.bx / 64) : 1u;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)b->cfg.blocks_per_cu * b->num_cus,
-                                                       std::max<uint32_t>(b->ntiles, 1u));
+                                                       std::max<uint64_t>((b->ntiles + per_block - 1) / per_block, 1u));
     return launch_batch(b->storage, b->pool[from], b->pool[1 - from], b->d_inst, b->d_tiles, b->ntiles, b->route,
-                        dim3(grid), dim3(b->cfg.bx), st);
+                        b->rows, dim3(grid), dim3(b->cfg.bx), st);
 }
 
 clbm_status build_graph(clbm_batch *b, int parity) {
@@ -291,8 +347,7 @@ clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *byte
         if (inst[i].storage != inst[0].storage) return fail(CLBM_EINVAL, "instance %d: storage differs", i);
         if (inst[i].collision == CLBM_COLLIDE_SRT)
             return fail(CLBM_EINVAL, "instance %d: batches run the cascaded scheme only", i);
-        if (inst[i].layout != CLBM_LAYOUT_PLANES)
-            return fail(CLBM_EINVAL, "instance %d: batches use the planes layout", i);
+        if (inst[i].layout != inst[0].layout) return fail(CLBM_EINVAL, "instance %d: layout differs", i);
         // the row of a node within its layer comes from a float estimate with
         // one correction, exact while a layer has at most 2^22 nodes
         if ((int64_t)inst[i].nx * inst[i].ny > ((int64_t)1 << 22))
@@ -317,6 +372,7 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
     clbm_batch *b = new clbm_batch();
     b->count = count;
     b->storage = inst[0].storage;
+    b->rows = inst[0].layout == CLBM_LAYOUT_ROWS;
     b->route = 0;
     for (int i = 0; i < count; ++i)
         if (route_of(&inst[i]) == 1) b->route = 1;   // one form for the whole batch
@@ -331,7 +387,7 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
         b->rf.push_back(make_relax<float>(&inst[i]));
         b->base.push_back(off);
         b->forced.push_back(inst[i].force[0] != 0.0 || inst[i].force[1] != 0.0 || inst[i].force[2] != 0.0);
-        off += plane_stride_of(&inst[i]) * Q;
+        off += (int64_t)(instance_bytes(&inst[i]) / elem_bytes(inst[i].storage));
     }
     b->pool[0] = pool_a;
     b->pool[1] = pool_b;
@@ -460,9 +516,16 @@ clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream) {
             c.fuse_steps = 1;
             c.fuse_rows = 8;
             c.fuse_planes = 1;
-            HIP_TRY(launch_step(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
-                                b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
-                    "clbm_batch_step_each");
+            if (b->rows) {
+                if (nx >= 64) c.by = 1;         // one lattice row per block, as for a single lattice
+                HIP_TRY(launch_step_rows(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
+                                         b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
+                        "clbm_batch_step_each");
+            } else {
+                HIP_TRY(launch_step(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
+                                    b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
+                        "clbm_batch_step_each");
+            }
         }
         b->cur = 1 - b->cur;
         b->steps_done++;

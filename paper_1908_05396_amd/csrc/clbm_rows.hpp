@@ -82,4 +82,81 @@ inline RowLaunch row_launch(const Geom &g, int bx, int by, int remap) {
     return L;
 }
 
+// Node x of row (y, z), y and z uniform over the wave; Face: the row lies on
+// a y or z face.
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face>
+__device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p, int x,
+                                int y, int z) {
+    constexpr uint32_t es = sizeof(S);
+    const int64_t r = (int64_t)z * g.ny + y;
+    // Each direction reads a run of its source row through a base one value
+    // before the run; the lane offset selects x - cx(a) + 1, wrapped on a
+    // periodic x axis.  Offsets stay within nx + 2 values of the base, and
+    // every address lies inside the buffer (x - cx(a) = -1 or nx reaches the
+    // neighbouring run of the same row group, which the x-face rule below
+    // replaces).
+    // (the ranges pass through readfirstlane so that the compiler keeps the
+    // descriptors in scalar registers)
+    const uint32_t range = __builtin_amdgcn_readfirstlane((uint32_t)(g.nx + 2) * es);
+    const uint32_t o0 = (uint32_t)(x + 1) * es;
+    const uint32_t op = (g.px && x == 0) ? range - 2 * es : (uint32_t)x * es;      // cx = +1: source x - 1
+    const uint32_t om = (g.px && x == g.nx - 1) ? es : (uint32_t)(x + 2) * es;     // cx = -1: source x + 1
+    auto lane_off = [&](int a) { return cx(a) == 1 ? op : (cx(a) == -1 ? om : o0); };
+    auto run = [&](int a, int64_t row) {
+        return row_rsrc(A + row * g.row + (int64_t)a * g.nx - 1, range);
+    };
+    // the node's own row group, for the bounce-back values (slot in the lane offset)
+    const __amdgpu_buffer_rsrc_t own_rsrc =
+        row_rsrc(A + r * g.row, __builtin_amdgcn_readfirstlane((uint32_t)Q * (uint32_t)g.nx * es));
+    auto own = [&](int a) {
+        return (T)RawBits<S>::template load<LdAux>(own_rsrc, (uint32_t)(opp(a) * g.nx + x) * es);
+    };
+    T d[Q];
+    if constexpr (!Face) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            d[a] = (T)RawBits<S>::template load<LdAux>(run(a, r - cy(a) - (int64_t)cz(a) * g.ny), lane_off(a));
+    } else {
+        // rows on a y or z face: per direction (uniformly) the source row is
+        // inside, wrapped on a periodic axis, or a ghost: half-way bounce-back
+        // returns the node's own population opposite to a, plus the
+        // moving-wall term for a ghost in the lid plane
+        const int m = g.lid_mask;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            int sy = y - cy(a), sz = z - cz(a);
+            bool wall = false;
+            if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
+            if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
+            if (!wall) {
+                d[a] = (T)RawBits<S>::template load<LdAux>(run(a, (int64_t)sz * g.ny + sy), lane_off(a));
+            } else {
+                const int sx = x - cx(a);
+                const bool in_lid = ((m & 4) && sy == -1) || ((m & 8) && sy == g.ny) || ((m & 16) && sz == -1) ||
+                                    ((m & 32) && sz == g.nz) || ((m & 1) && sx == -1) || ((m & 2) && sx == g.nx);
+                d[a] = wall_value<T>(own(a), p, a, in_lid);
+            }
+        }
+    }
+    // lanes on a non-periodic x face: directions whose source row is inside
+    // the lattice but whose source column is a ghost
+    if (!g.px && (x == 0 || x == g.nx - 1)) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            if (cx(a) == 0 || !((x == 0 && cx(a) == 1) || (x == g.nx - 1 && cx(a) == -1))) continue;
+            const int sy = y - cy(a), sz = z - cz(a);
+            const bool row_wall = (!g.py && (sy < 0 || sy >= g.ny)) || (!g.pz && (sz < 0 || sz >= g.nz));
+            if (row_wall) continue;     // bounced back above, with the lid term of every ghost coordinate
+            d[a] = wall_value<T>(own(a), p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
+        }
+    }
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    const uint32_t srange = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
+    S *out = B + r * g.row;
+    const uint32_t lane = (uint32_t)x * es;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+        RawBits<S>::template store<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a]);
+}
+
 }  // namespace clbm

@@ -125,7 +125,13 @@ def test_batch_size_validates_each_instance(clbm):
     assert "instance 1" in clbm.load().clbm_last_error().decode()
     arr[1] = clbm.params_from_spec(specs[1], "f32", layout="rows")
     assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL
-    assert "planes layout" in clbm.load().clbm_last_error().decode()
+    assert "layout differs" in clbm.load().clbm_last_error().decode()
+    # all in the row layout: each instance rounded up to 256 bytes
+    rows = (clbm.Params * 2)()
+    for i, sp in enumerate(specs):
+        rows[i] = clbm.params_from_spec(sp, "f32", layout="rows")
+    assert clbm.load().clbm_batch_size(rows, 2, ctypes.byref(n)) == 0
+    assert n.value == sum((clbm.buffer_size(rows[i])[1] + 255) // 256 * 256 for i in range(2))
     arr[1] = clbm.params_from_spec(specs[1], "f32", layout="planes")
     arr[1].K = -1.0
     assert clbm.load().clbm_batch_size(arr, 2, ctypes.byref(n)) == clbm.CLBM_EINVAL

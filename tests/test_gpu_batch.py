@@ -25,6 +25,8 @@ def _mixed_specs():
     return [
         W.cavity(12, 0.05, 0.6, 50.0, name="b_cav12"),
         W.cavity(16, 0.05, 1.4, 80.0, name="b_cav16").with_(nx=70, ny=9, name="b_cav70x9x16"),
+        W.cavity(10, 0.04, 0.9, 60.0, name="b_cav128").with_(nx=128, ny=6, nz=5, lid_face=W.LID_MX,
+                                                             lid_velocity=(0.0, 0.04, 0.01)),
         W.poiseuille(6, 20, 5, n=0.8, Re=10.0, umax=0.02, name="b_chan"),
         W.LatticeSpec(nx=9, ny=11, nz=7, K=0.02, n=1.0, periodic=(1, 1, 1), force=(2e-5, -1e-5, 0.0),
                       name="b_periodic"),
@@ -33,13 +35,14 @@ def _mixed_specs():
 
 # the fully periodic box has no walls to drive it: a larger perturbation
 # keeps its velocities well above the FP64 noise floor
-EPS = [1e-3, 1e-3, 1e-3, 5e-2]
+EPS = [1e-3, 1e-3, 1e-3, 1e-3, 5e-2]
 
 
-def test_batch_matches_oracle_per_instance(clbm):
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_batch_matches_oracle_per_instance(clbm, layout):
     specs = _mixed_specs()
     steps = 70
-    b = clbm.Batch(specs, storage="f64")
+    b = clbm.Batch(specs, storage="f64", layout=layout)
     b.init_rest()
     for i, sp in enumerate(specs):
         b.init_populations(i, W.perturbed_populations(sp, 40 + i, EPS[i], device="cuda"))
@@ -47,7 +50,7 @@ def test_batch_matches_oracle_per_instance(clbm):
     b.step(steps)          # three graph replays and ten plain launches
     torch.cuda.synchronize()
     for i, sp in enumerate(specs):
-        print(f"[gpu] batch instance {i} {sp.name}", flush=True)
+        print(f"[gpu] batch {layout} instance {i} {sp.name}", flush=True)
         _, u = b.macroscopic(i)
         f = oracle.run(sp, W.perturbed_populations(sp, 40 + i, EPS[i]).numpy(), steps)
         _, u_ref = oracle.macroscopic(sp, f)
@@ -62,12 +65,13 @@ def test_batch_matches_oracle_per_instance(clbm):
 ATOL = {"f32": 2e-6, "f16": 2e-4}
 
 
+@pytest.mark.parametrize("layout", ["rows", "planes"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_batch_equals_per_instance_launches(clbm, storage):
+def test_batch_equals_per_instance_launches(clbm, storage, layout):
     specs = _mixed_specs()
     outs = []
     for mode in ("batch", "each"):
-        b = clbm.Batch(specs, storage=storage)
+        b = clbm.Batch(specs, storage=storage, layout=layout)
         b.init_rest()
         for i, sp in enumerate(specs):
             b.init_populations(i, W.perturbed_populations(sp, 7 + i, 1e-3, device="cuda"))
@@ -81,11 +85,12 @@ def test_batch_equals_per_instance_launches(clbm, storage):
         assert err < ATOL[storage]
 
 
-def test_graph_replay_equals_plain_launches(clbm):
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_graph_replay_equals_plain_launches(clbm, layout):
     specs = _mixed_specs()
     outs = []
     for k in (0, 8, 9):
-        b = clbm.Batch(specs, storage="f32")
+        b = clbm.Batch(specs, storage="f32", layout=layout)
         b.init_rest()
         b.set_config(graph_steps=k)
         b.step(5)
@@ -116,17 +121,19 @@ def test_autotune_keeps_state_and_caches(clbm, tmp_path):
     assert b3.get_config() != cfg or cfg == clbm.Batch(specs[:2], storage="f32").get_config()
 
 
-def test_config4_batch_full_size(clbm):
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_config4_batch_full_size(clbm, layout):
     """The 64-cavity batch (edges 32..96, n in [0.4, 1.6], Re in [50, 1000])
     at full size: the persistent graph-replayed launch agrees with one launch
     per instance, and every instance keeps its mass (closed cavities)."""
     specs = W.config_batch()
-    b = clbm.Batch(specs, storage="f32")
+    print(f"[gpu] config-4 batch {layout}", flush=True)
+    b = clbm.Batch(specs, storage="f32", layout=layout)
     b.init_rest()
     r0 = b.reduce()
     b.autotune()
     b.step(40)
-    ref = clbm.Batch(specs, storage="f32")
+    ref = clbm.Batch(specs, storage="f32", layout=layout)
     ref.init_rest()
     ref.step_each(40)
     r1 = b.reduce(raise_unstable=False)
