@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 BYTES_PER_LUP = {"f64": 304, "f32": 152, "f16": 76}   # 19 reads + 19 writes per node update
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_05396_amd", "csrc", f)
-                  for f in ("clbm_device.hpp", "clbm_internal.hpp", "clbm_kernels.hip", "clbm_rows.hip",
-                            "clbm_fused.hip")]
+                  for f in ("clbm_device.hpp", "clbm_internal.hpp", "clbm_rows.hpp", "clbm_kernels.hip",
+                            "clbm_rows.hip", "clbm_fused.hip")]
 # the one-step kernel of each state layout
 STEP_KERNEL = {"rows": "stream_collide_rows", "planes": "stream_collide"}
 
