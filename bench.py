@@ -400,6 +400,21 @@ def main():
                 "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
                                        / HBM_PEAK_GBS, 4)}
 
+    # the library's autotuner on the same workload (FP32, row layout, after a short warm-up)
+    autotuned = None
+    if not (args.no_variants or args.no_extras):
+        lat = clbm.Lattice(spec, storage="f32", track_residual=False)
+        lat.init_rest()
+        lat.step(20)
+        default = lat.get_launch()
+        cfg, ms = lat.autotune()
+        autotuned = {"storage": "f32", "default_launch": default, "best_launch": cfg,
+                     "best_ms_per_step": round(ms, 4),
+                     "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+
     # the single-relaxation-time comparison model on the same workload (FP32)
     comparison = None
     if not (args.no_variants or args.no_extras):
@@ -451,6 +466,7 @@ def main():
         "variants": variants,
         "other_launch_form": launch_forms,
         "planes_layout": planes_layout,
+        "autotune": autotuned,
         "srt_comparison": comparison,
         "in_place": in_place,
         "accuracy": accuracy,

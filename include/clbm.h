@@ -242,6 +242,16 @@ clbm_status clbm_get_launch(clbm_lattice *h, clbm_launch *cfg);
 clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by);
 clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by);
 
+/* Time one step per launch over block widths 64..512 (multiples of 64, up
+ * to the lattice width rounded up to 64), 1, 2 or 4 rows per block, both tile
+ * orders and both cache hints, and the two-step configuration in place if
+ * fuse_steps = 2, on the current state; keep the fastest and report it and its
+ * time per step in ms (either output may be NULL).  The trial launches read
+ * the current buffer and write the other one, so the state is unchanged; the
+ * call synchronizes its stream.  Refused (EINVAL) for the one-buffer form,
+ * whose steps overwrite the state, and before an init call (ESTATE). */
+clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, double *best_ms);
+
 clbm_status clbm_destroy(clbm_lattice *h);
 
 /* Message for the last failing call on this thread ("" if none). */

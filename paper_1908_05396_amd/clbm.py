@@ -84,6 +84,7 @@ SIGNATURES = {
     "clbm_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(Launch)]),
     "clbm_set_block": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "clbm_get_block": (ctypes.c_int, [_VP, _I32P, _I32P]),
+    "clbm_autotune": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(Launch), _DP]),
     "clbm_destroy": (ctypes.c_int, [_VP]),
     "clbm_last_error": (ctypes.c_char_p, []),
     "clbm_version": (ctypes.c_char_p, []),
@@ -315,6 +316,14 @@ class Lattice:
     # -- launch shape ------------------------------------------------------
     def set_block(self, bx: int, by: int):
         _check(load().clbm_set_block(self._h, int(bx), int(by)))
+
+    def autotune(self, stream=None):
+        """Time block shapes, tile orders and cache hints on the current state
+        (left unchanged) and keep the fastest; returns (launch dict, ms per step)."""
+        c = Launch()
+        ms = ctypes.c_double()
+        _check(load().clbm_autotune(self._h, _stream(stream), ctypes.byref(c), ctypes.byref(ms)))
+        return {k: getattr(c, k) for k, _ in Launch._fields_ if k != "reserved"}, float(ms.value)
 
     def set_launch(self, **kw):
         c = Launch()

@@ -1,6 +1,7 @@
 // C-ABI of the D3Q19 cascaded power-law LBM library (declared in clbm.h):
 // parameter validation, handles, kernel parameter set-up and launches.
 #include <array>
+#include <vector>
 
 #include "clbm_host.hpp"
 
@@ -360,6 +361,76 @@ clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by) {
     c.bx = bx;
     c.by = by;
     return clbm_set_launch(h, &c);
+}
+
+clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, double *best_ms) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (h->in_place) return fail(CLBM_EINVAL, "autotune: the one-buffer form overwrites its state");
+    if (!h->initialized) return fail(CLBM_ESTATE, "autotune needs an initialised state");
+    hipStream_t st = (hipStream_t)stream;
+    const int maxt = h->prm.storage == CLBM_F64 ? 256 : 512;
+    const int wmax = (h->prm.nx + 63) / 64 * 64;
+    // candidates: one step per launch over block shapes, tile orders and cache
+    // hints, plus the two-step configuration in place if there is one
+    std::vector<StepLaunch> cands;
+    for (int bx = 64; bx <= 512 && (bx <= wmax || bx == 64); bx *= 2)
+        for (int by = 1; by <= 4; by *= 2) {
+            if (bx * by > maxt || (by > 1 && by > h->prm.ny)) continue;
+            for (int mode = 0; mode < 8; ++mode) {
+                StepLaunch c = h->launch;
+                c.fuse_steps = 1;
+                c.bx = bx;
+                c.by = by;
+                c.xcd_remap = mode & 1;
+                c.nt_loads = (mode >> 1) & 1;
+                c.nt_stores = (mode >> 2) & 1;
+                cands.push_back(c);
+            }
+        }
+    if (h->launch.fuse_steps == 2) cands.push_back(h->launch);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "autotune: event");
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "autotune: event");
+    }
+    // a trial launch reads the current buffer and writes the other one
+    auto trial = [&](const StepLaunch &c) -> hipError_t {
+        const void *A = h->buf[h->cur];
+        void *B = h->buf[1 - h->cur];
+        if (c.fuse_steps == 2)
+            return launch_step2(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c.fuse_rows,
+                                c.fuse_planes, st);
+        if (h->geom.rows)
+            return launch_step_rows(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c, st);
+        return launch_step(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c, st);
+    };
+    const int reps = 3;
+    StepLaunch win = h->launch;
+    double win_ms = 1e300;
+    for (const StepLaunch &c : cands) {
+        e = trial(c);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = trial(c);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        const double per_step = ms / reps / (c.fuse_steps == 2 ? 2.0 : 1.0);
+        if (per_step < win_ms) {
+            win_ms = per_step;
+            win = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune: trial launch");
+    h->launch = win;
+    if (best) clbm_get_launch(h, best);
+    if (best_ms) *best_ms = win_ms;
+    return CLBM_OK;
 }
 
 clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by) {

@@ -113,3 +113,32 @@ def test_rows_rest_state_and_reductions(clbm):
     assert abs(r1["mass"] - spec.nodes) < 1e-11 * spec.nodes
     for k in ("mass", "momentum_x", "momentum_y", "momentum_z", "umax", "kinetic"):
         assert abs(r1[k] - r2[k]) <= 1e-12 * max(1.0, abs(r2[k])), k
+
+
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_autotune_keeps_state_and_results(clbm, layout):
+    """clbm_autotune times launches into the spare buffer: the state is
+    unchanged, and stepping with the chosen launch gives the same bits as the
+    default launch."""
+    spec = _geometries()["lid_py_130x12x9"]
+    print(f"[gpu] autotune {layout}", flush=True)
+    outs = []
+    for tune in (False, True):
+        lat = clbm.Lattice(spec, storage="f32", track_residual=False, layout=layout)
+        lat.init_populations(W.perturbed_populations(spec, 12, 1e-2, device="cuda"))
+        lat.step(3)
+        if tune:
+            before = lat.populations().cpu().numpy()
+            cfg, ms = lat.autotune()
+            assert ms > 0 and cfg["bx"] % 64 == 0 and cfg["fuse_steps"] == 1 and lat.get_launch() == cfg
+            assert np.array_equal(before, lat.populations().cpu().numpy())
+            assert lat.state() == (1, 3)
+        lat.step(5)
+        outs.append(lat.populations().cpu().numpy())
+        lat.close()
+    assert np.array_equal(outs[0], outs[1])
+    ip = clbm.Lattice(spec, storage="f32", in_place=True, layout=layout)
+    ip.init_rest()
+    with pytest.raises(clbm.ClbmError):
+        ip.autotune()
+    ip.close()
