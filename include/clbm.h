@@ -112,8 +112,9 @@ typedef struct {
     int32_t attractor_literal; /* 0: fourth-order attractors kxx*kyy/rho (default);
                                   1: kxx*kyy as printed (linearly unstable, for study only) */
     int32_t track_residual;    /* 1: keep a velocity snapshot for the steady-state residual */
-    int32_t plane_pad;         /* extra elements between population planes (>= 0), on top of the
-                                  256-byte rounding; -1: library default (see clbm_buffer_size) */
+    int32_t plane_pad;         /* planes layout: extra elements between population planes (>= 0), on
+                                  top of the 256-byte rounding; -1: library default (see
+                                  clbm_buffer_size); unused in the row layout */
     int32_t collision;         /* clbm_collision: which algebraic form of the collision runs */
     int32_t layout;            /* clbm_layout of the state buffers */
     int32_t reserved;          /* must be 0 */

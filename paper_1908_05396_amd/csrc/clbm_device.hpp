@@ -82,10 +82,11 @@ __device__ inline int64_t elem_i(const Geom &g, int a, int64_t i) {
 }
 
 // ---------------------------------------------------------------------------
-// Plane access through raw buffer descriptors: one descriptor per population
-// plane (base = plane start, range = n elements), 32-bit byte offsets from a
-// VGPR.  Offsets outside the range return 0 without touching memory, so the
-// interior pull can run unguarded and edge lanes are patched afterwards.
+// Planes layout: access through raw buffer descriptors, one descriptor per
+// population plane (base = plane start, range = n elements), 32-bit byte
+// offsets from a VGPR.  Offsets outside the range return 0 without touching
+// memory, so the interior pull can run unguarded and edge lanes are patched
+// afterwards.
 // ---------------------------------------------------------------------------
 constexpr int kBufferFlags = 0x00020000;   // raw (untyped) buffer, gfx9 family
 

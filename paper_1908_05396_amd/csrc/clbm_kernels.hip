@@ -1,7 +1,8 @@
 // Kernels of the D3Q19 cascaded power-law LBM for gfx950 and their launchers.
 //
-//   stream_collide  one time step: pull gather + collision + store (Sec. 3)
-//   init_collide    collide a caller-supplied FP64 state once (time 0)
+//   stream_collide  one time step in the planes layout: pull gather + collision
+//                   + store (Sec. 3); the row layout's step is in clbm_rows.hip
+//   init_collide    collide a caller-supplied FP64 state once (time 0), either layout
 //   macroscopic     rho and u from the stored post-collision state
 //   export          f = w + stored deviation, as FP64
 //   reduce          FP64 block partials of mass, momentum, residual, NaNs
