@@ -46,10 +46,16 @@ STEP_KERNEL = {"rows": "stream_collide_rows", "planes": "stream_collide"}
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernels' code: the sources with comments and blank
+    lines removed, so that a profile stays valid across comment edits."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
