@@ -57,6 +57,9 @@ def _geometries():
         "wide_box": W.LatticeSpec(nx=64, ny=5, nz=6, K=0.02, n=0.9, periodic=(1, 1, 1), name="wide_box"),
         "wide_forced": W.poiseuille(64, 16, 4, n=0.6, Re=5.0, umax=0.02),
         "wide_srt": cav.with_(nx=72, ny=9, nz=8, model="srt"),
+        "wide_slab_ny1": W.LatticeSpec(nx=64, ny=1, nz=5, K=0.02, n=0.8, periodic=(1, 1, 0), name="wide_slab_ny1"),
+        "wide_slab_2x2": W.LatticeSpec(nx=64, ny=2, nz=2, K=0.03, n=1.2, lid_face=W.LID_PY,
+                                       lid_velocity=(0.05, 0.0, 0.01), name="wide_slab_2x2"),
     }
 
 

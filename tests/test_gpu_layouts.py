@@ -46,6 +46,11 @@ def _geometries():
         "periodic_y_lid_pz_64x9x7": base.with_(nx=64, ny=9, nz=7, periodic=(0, 1, 0), lid_face=W.LID_PZ,
                                                lid_velocity=(0.04, 0.01, 0.0)),
         "channel_forced_64x16x4": W.poiseuille(64, 16, 4, n=0.6, Re=5.0, umax=0.02),
+        # one row per y (ny = 1) or per z (nz = 1): every row is a face row
+        "slab_ny1_64x1x5": W.LatticeSpec(nx=64, ny=1, nz=5, K=0.02, n=0.8, periodic=(1, 1, 0), name="slab_ny1"),
+        "slab_nz1_96x6x1": base.with_(nx=96, ny=6, nz=1, periodic=(0, 0, 1)),
+        "slab_ny2_nz2_64x2x2": W.LatticeSpec(nx=64, ny=2, nz=2, K=0.03, n=1.2, lid_face=W.LID_PY,
+                                             lid_velocity=(0.05, 0.0, 0.01), name="slab_2x2"),
         "ghat_general_80x9x7": base.with_(nx=80, ny=9, nz=7, **omegas),
         "srt_72x9x8": base.with_(nx=72, ny=9, nz=8, model="srt"),
     }
