@@ -277,6 +277,9 @@ typedef struct {
                                   rows: bx / 64 waves, each on its own items; by must be 1 */
     int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu x 256 workgroups (1..64) */
     int32_t graph_steps;       /* steps per captured graph (0: plain launches) */
+    int32_t nt_stores;         /* 1: non-temporal (streaming) stores, 0: plain stores (default: the
+                                  short runs of small lattices leave partial cache lines, which plain
+                                  stores let the cache merge) */
 } clbm_batch_config;
 
 /* Bytes each of the two pools must hold for these instances. */
@@ -308,9 +311,10 @@ clbm_status clbm_batch_populations(clbm_batch *b, int32_t i, double *f_dev, void
  * (synchronizes; EUNSTABLE if any instance holds non-finite values). */
 clbm_status clbm_batch_reduce(clbm_batch *b, double *out, void *stream);
 
-/* Time candidate launch configurations on the current state (each trial
- * writes only the spare pool, so the state is unchanged), keep the fastest,
- * and append it to the tune cache when one was given.  `best` (nullable)
+/* Time candidate launch configurations (bx, blocks_per_cu, nt_stores) on the
+ * current state (each trial writes only the spare pool, so the state is
+ * unchanged), keep the fastest, and append it to the tune cache when one was
+ * given.  `best` (nullable)
  * receives it; `best_ms` (nullable) its time per step. */
 clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *best, double *best_ms);
 

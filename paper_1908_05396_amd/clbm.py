@@ -59,7 +59,7 @@ class Launch(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("nt_stores", ctypes.c_int32)]
 
 
 _lib = None

@@ -30,7 +30,7 @@ template <typename T> struct BatchInst {
     int32_t forced;
 };
 
-template <typename S, typename T, int Route>
+template <typename S, typename T, int Route, int StAux>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
                   const int32_t *__restrict__ tile_inst, uint32_t ntiles) {
@@ -57,19 +57,19 @@ batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         else
             collide<T, false, Route, NewtonSteps<S>::value>(d, p, nullptr);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) Plane<S, 2>::store(B + base, g, a, self, d[a]);
+        for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B + base, g, a, self, d[a]);
     }
 }
 
-template <typename S, typename T, bool Forced, int Route>
+template <typename S, typename T, bool Forced, int Route, int StAux>
 __device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T> &p, int x, int y, int z) {
     if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1)
-        row_step<S, T, Forced, 0, 2, Route, true>(A, B, g, p, x, y, z);
+        row_step<S, T, Forced, 0, StAux, Route, true>(A, B, g, p, x, y, z);
     else
-        row_step<S, T, Forced, 0, 2, Route, false>(A, B, g, p, x, y, z);
+        row_step<S, T, Forced, 0, StAux, Route, false>(A, B, g, p, x, y, z);
 }
 
-template <typename S, typename T, int Route>
+template <typename S, typename T, int Route, int StAux>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
                   const int32_t *__restrict__ tile_inst, uint32_t ntiles) {
@@ -88,39 +88,46 @@ batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         if (x >= g.nx) continue;
         const Relax<T> &p = inst[i].p;
         if (inst[i].forced)
-            batch_row<S, T, true, Route>(A + base, B + base, g, p, x, y, z);
+            batch_row<S, T, true, Route, StAux>(A + base, B + base, g, p, x, y, z);
         else
-            batch_row<S, T, false, Route>(A + base, B + base, g, p, x, y, z);
+            batch_row<S, T, false, Route, StAux>(A + base, B + base, g, p, x, y, z);
     }
+}
+
+template <typename S, typename T, int StAux>
+static hipError_t launch_batch_h(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
+                                 int route, bool rows, dim3 grid, dim3 block, hipStream_t st) {
+    const S *a = (const S *)A;
+    S *b = (S *)B;
+    const BatchInst<T> *d = (const BatchInst<T> *)inst;
+    if (rows) {
+        if (route == 0)
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+        else
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+        return hipGetLastError();
+    }
+    if (route == 0)
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+    else
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+    return hipGetLastError();
 }
 
 template <typename S, typename T>
 static hipError_t launch_batch_t(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
-                                 int route, bool rows, dim3 grid, dim3 block, hipStream_t st) {
-    if (rows) {
-        if (route == 0)
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0>), grid, block, 0, st, (const S *)A, (S *)B,
-                               (const BatchInst<T> *)inst, tiles, ntiles);
-        else
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1>), grid, block, 0, st, (const S *)A, (S *)B,
-                               (const BatchInst<T> *)inst, tiles, ntiles);
-        return hipGetLastError();
-    }
-    if (route == 0)
-        hipLaunchKernelGGL((batch_step_kernel<S, T, 0>), grid, block, 0, st, (const S *)A, (S *)B,
-                           (const BatchInst<T> *)inst, tiles, ntiles);
-    else
-        hipLaunchKernelGGL((batch_step_kernel<S, T, 1>), grid, block, 0, st, (const S *)A, (S *)B,
-                           (const BatchInst<T> *)inst, tiles, ntiles);
-    return hipGetLastError();
+                                 int route, bool rows, bool nt, dim3 grid, dim3 block, hipStream_t st) {
+    return nt ? launch_batch_h<S, T, 2>(A, B, inst, tiles, ntiles, route, rows, grid, block, st)
+              : launch_batch_h<S, T, 0>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
 }
 
 static hipError_t launch_batch(int storage, const void *A, void *B, const void *inst, const int32_t *tiles,
-                               uint32_t ntiles, int route, bool rows, dim3 grid, dim3 block, hipStream_t st) {
+                               uint32_t ntiles, int route, bool rows, bool nt, dim3 grid, dim3 block,
+                               hipStream_t st) {
     switch (storage) {
-    case 0: return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
-    case 1: return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
-    default: return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
+    case 0: return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, nt, grid, block, st);
+    case 1: return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, nt, grid, block, st);
+    default: return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, nt, grid, block, st);
     }
 }
 
@@ -195,6 +202,7 @@ clbm_status check_config(const clbm_batch *b, const clbm_batch_config *c) {
         return fail(CLBM_EINVAL, "batch tile %d x %d: need by = 1 and bx a multiple of 64, <= %d", c->bx, c->by, mt);
     if (c->blocks_per_cu < 1 || c->blocks_per_cu > 64) return fail(CLBM_EINVAL, "blocks_per_cu must lie in 1..64");
     if (c->graph_steps < 0 || c->graph_steps > 4096) return fail(CLBM_EINVAL, "graph_steps must lie in 0..4096");
+    if (c->nt_stores != 0 && c->nt_stores != 1) return fail(CLBM_EINVAL, "nt_stores must be 0 or 1");
     return CLBM_OK;
 }
 
@@ -252,7 +260,7 @@ hipError_t launch_one_step(clbm_batch *b, int from, hipStream_t st) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)b->cfg.blocks_per_cu * b->num_cus,
                                                        std::max<uint64_t>((b->ntiles + per_block - 1) / per_block, 1u));
     return launch_batch(b->storage, b->pool[from], b->pool[1 - from], b->d_inst, b->d_tiles, b->ntiles, b->route,
-                        b->rows, dim3(grid), dim3(b->cfg.bx), st);
+                        b->rows, b->cfg.nt_stores != 0, dim3(grid), dim3(b->cfg.bx), st);
 }
 
 clbm_status build_graph(clbm_batch *b, int parity) {
@@ -305,7 +313,8 @@ bool read_cache(clbm_batch *b, clbm_batch_config *out) {
     char key[256];
     clbm_batch_config c;
     bool found = false;
-    while (fscanf(fh, "%255s %d %d %d %d", key, &c.bx, &c.by, &c.blocks_per_cu, &c.graph_steps) == 5) {
+    while (fscanf(fh, "%255s %d %d %d %d %d", key, &c.bx, &c.by, &c.blocks_per_cu, &c.graph_steps, &c.nt_stores) ==
+           6) {
         if (b->cache_key == key && check_config(b, &c) == CLBM_OK) {
             *out = c;
             found = true;       // the last entry for a key wins
@@ -319,7 +328,8 @@ void append_cache(clbm_batch *b, const clbm_batch_config &c, double ms) {
     if (b->cache_path.empty()) return;
     FILE *fh = fopen(b->cache_path.c_str(), "a");
     if (!fh) return;
-    fprintf(fh, "%s %d %d %d %d\n", b->cache_key.c_str(), c.bx, c.by, c.blocks_per_cu, c.graph_steps);
+    fprintf(fh, "%s %d %d %d %d %d\n", b->cache_key.c_str(), c.bx, c.by, c.blocks_per_cu, c.graph_steps,
+            c.nt_stores);
     (void)ms;
     fclose(fh);
 }
@@ -396,6 +406,7 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
     b->cfg.by = 1;
     b->cfg.blocks_per_cu = 8;
     b->cfg.graph_steps = 20;
+    b->cfg.nt_stores = 0;
     b->num_cus = 256;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -629,8 +640,9 @@ clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *
         c.bx = sh[0];
         c.by = sh[1];
         if (check_config(b, &c) != CLBM_OK) continue;
-        for (int bpc : bpcs) {
-            c.blocks_per_cu = bpc;
+        for (int k = 0; k < 8; ++k) {
+            c.blocks_per_cu = bpcs[k % 4];
+            c.nt_stores = k / 4;
             if ((result = clbm_batch_set_config(b, &c)) != CLBM_OK) break;
             // trials read the state and write the spare pool: the state is unchanged
             hipError_t e = launch_one_step(b, b->cur, st);

@@ -93,6 +93,10 @@ inline clbm_status validate(const clbm_params *p) {
         return fail(CLBM_EINVAL, "lattice of %lld nodes: one population plane exceeds 4 GiB", (long long)N);
     if (N >= ((int64_t)1 << 31))
         return fail(CLBM_EINVAL, "lattice of %lld nodes: at most 2^31 - 1 nodes", (long long)N);
+    // rows: the descriptors of a wave span at most 20 runs of nx + 64 values
+    if (p->layout == CLBM_LAYOUT_ROWS &&
+        (int64_t)(Q + 1) * (p->nx + 64) * (int64_t)elem_bytes(p->storage) >= ((int64_t)1 << 31))
+        return fail(CLBM_EINVAL, "row of %d values too long for the row layout", p->nx);
     if (!(p->K > 0.0) || !isfinite(p->K)) return fail(CLBM_EINVAL, "K must be finite and > 0");
     if (!(p->n > 0.0) || !isfinite(p->n)) return fail(CLBM_EINVAL, "n must be finite and > 0");
     if (!(p->nu_min > 0.0) || !(p->nu_max > p->nu_min) || !isfinite(p->nu_max))

@@ -52,6 +52,21 @@ def test_kernel_tables_match_paper(clbm):
     assert np.array_equal(w, np.array(vals))
 
 
+def test_batch_config_struct_matches_header(clbm):
+    """The binding's clbm_batch_config has the header's int32 fields in order."""
+    with open(os.path.join(ROOT, "include", "clbm.h")) as fh:
+        text = fh.read()
+    body = text[text.index("typedef struct {", text.index("typedef struct clbm_batch clbm_batch;")):
+                text.index("} clbm_batch_config;")]
+    names = []
+    for line in body.splitlines():
+        line = line.split("/*")[0].strip()
+        if line.startswith("int32_t"):
+            names += [n.strip() for n in line[len("int32_t"):].rstrip(";").split(",")]
+    assert names == [k for k, _ in clbm.BatchConfig._fields_]
+    assert ctypes.sizeof(clbm.BatchConfig) == 4 * len(names)
+
+
 def test_params_struct_layout(clbm):
     assert ctypes.sizeof(clbm.Params) == 56 + 8 * (5 + 9 + 3 + 3 + 1)
     p = clbm.Params()
@@ -178,3 +193,9 @@ def test_size_limits_per_layout(clbm):
     with pytest.raises(clbm.ClbmError):
         clbm.buffer_size(clbm.params_from_spec(too_many, "f16", layout="rows"))
     clbm.buffer_size(clbm.params_from_spec(too_many.with_(nz=1023), "f16", layout="rows"))
+    # rows: a wave's descriptors span up to 20 runs of nx + 64 values, within a 2 GiB byte range
+    long_row = big.with_(nx=1 << 24, ny=1, nz=1)
+    with pytest.raises(clbm.ClbmError):
+        clbm.buffer_size(clbm.params_from_spec(long_row, "f64", layout="rows"))
+    clbm.buffer_size(clbm.params_from_spec(long_row, "f16", layout="rows"))
+    clbm.buffer_size(clbm.params_from_spec(long_row, "f64", layout="planes"))

@@ -30,12 +30,15 @@ def _mixed_specs():
         W.poiseuille(6, 20, 5, n=0.8, Re=10.0, umax=0.02, name="b_chan"),
         W.LatticeSpec(nx=9, ny=11, nz=7, K=0.02, n=1.0, periodic=(1, 1, 1), force=(2e-5, -1e-5, 0.0),
                       name="b_periodic"),
+        # a periodic x axis wider than one wave, and a lattice whose rows all lie on a z face (nz = 2)
+        W.cavity(8, 0.05, 1.1, 70.0, name="b_px100").with_(nx=100, ny=7, nz=6, periodic=(1, 0, 0)),
+        W.cavity(8, 0.04, 0.7, 40.0, name="b_slab").with_(nx=40, ny=5, nz=2, periodic=(0, 0, 1)),
     ]
 
 
 # the fully periodic box has no walls to drive it: a larger perturbation
 # keeps its velocities well above the FP64 noise floor
-EPS = [1e-3, 1e-3, 1e-3, 1e-3, 5e-2]
+EPS = [1e-3, 1e-3, 1e-3, 1e-3, 5e-2, 1e-3, 1e-3]
 
 
 @pytest.mark.parametrize("layout", ["rows", "planes"])
@@ -100,6 +103,29 @@ def test_graph_replay_equals_plain_launches(clbm, layout):
     for other in outs[1:]:
         for x, y in zip(outs[0], other):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_store_hint_gives_same_bits(clbm, layout):
+    """Plain and non-temporal stores (the nt_stores choice of the batch
+    configuration) write the same values."""
+    specs = _mixed_specs()
+    outs = []
+    for nt in (0, 1):
+        b = clbm.Batch(specs, storage="f32", layout=layout)
+        b.init_rest()
+        for i, sp in enumerate(specs):
+            b.init_populations(i, W.perturbed_populations(sp, 3 + i, 1e-3, device="cuda"))
+        b.set_config(nt_stores=nt)
+        assert b.get_config()["nt_stores"] == nt
+        b.step(12)
+        outs.append([b.populations(i).cpu().numpy() for i in range(len(specs))])
+        if nt == 1:
+            with pytest.raises(clbm.ClbmError):
+                b.set_config(nt_stores=2)
+        b.close()
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
 
 
 def test_autotune_keeps_state_and_caches(clbm, tmp_path):
