@@ -3,24 +3,26 @@
 
 Workload (default): lid-driven cubic cavity 512^3 (134.2 M nodes), Re = 3200,
 n = 0.75, lid velocity 0.04, rest start, 5000 steps; FP32 storage of f - w
-with FP32 arithmetic, row-interleaved state layout; the FP64 mass reduction
-every 100 steps tracks the mass drift.  One step = the fused pull
-stream-collide over the whole lattice: one launch for the rows off the y and
-z faces and one for the face rows (about 0.8% of the nodes at 512^3).
-The FP16-deviation and FP64 storage runs of the same workload end at the same
-step, and the errors of FP32 and FP16 against FP64 are reported on the
-centrelines u_x(y), u_y(x) and normwise over the whole field.
+with FP32 arithmetic; the FP64 mass reduction every 100 steps tracks the mass
+drift.  Each storage type runs in its faster launch form: FP32 two steps per
+launch (temporal blocking, planes layout; one launch = two full steps of the
+fused pull stream-collide), FP16 deviations and FP64 one step per launch in
+the row-interleaved layout (a launch for the rows off the y and z faces and
+one for the face rows).  The FP16-deviation and FP64 runs end at the same
+step as the FP32 run, and the errors of FP32 and FP16 against FP64 are
+reported on the centrelines u_x(y), u_y(x) and normwise over the whole field.
 
 Prints ONE JSON line: MLUPS of the timed region (exactly --steps steps after
 --warmup untimed ones, bracketed by device synchronisation), the roofline of
-the stream-collide step (algorithmic bytes per step / average step time
-measured with events on the launch stream, both launches of a step between
-the events), the planes layout and the two-step launch form, the FP16-deviation and FP64
-storage variants of the same workload, the 64-cavity batch (persistent
-graph-replayed launch vs one launch per instance), the achievable copy
-bandwidth, and the CPU oracle timed on the host cores on a bounded sample of
-the same workload.
+the stream-collide kernel (algorithmic bytes of the steps a launch advances /
+average launch time measured with events on the launch stream), the other
+launch form and the planes layout of each storage type, the FP16-deviation
+and FP64 storage variants of the same workload, the 64-cavity batch
+(persistent graph-replayed launch vs one launch per instance), the
+achievable copy bandwidth, and the CPU oracle timed on the host cores on a
+bounded sample of the same workload.
 """
+
 from __future__ import annotations
 
 import argparse
@@ -99,20 +101,33 @@ def accuracy_vs(torch, runs, ref_key, U, L):
     return out
 
 
-# the launch form the library does not pick by default for a storage type
-OTHER_FORM = "other"
+# Two steps per launch (planes layout) for each storage type: the fastest
+# patch height, z chunk, tile order and store hint of a sweep at 512^3
+# (rows 8/12/16 x planes 4..32 x both orders x both hints).
+TWO_STEP = {"f32": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0},
+            "f16": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0},
+            "f64": {"fuse_steps": 2, "fuse_rows": 8, "fuse_planes": 32, "xcd_remap": 0, "nt_stores": 1}}
+# The faster form per storage type at 512^3: FP32 two steps per launch (it
+# moves ~0.55x the bytes of two one-step launches); FP16 storage, bound by its
+# arithmetic, and FP64 one step per launch in the row layout.
+BEST_FORM = {"f32": "two", "f16": "one", "f64": "one"}
+
+
+def launch_of(form, storage, spec):
+    """Launch dict of a form ("one": library default, "two": TWO_STEP)."""
+    if form != "two":
+        return None
+    c = dict(TWO_STEP[storage])
+    c["fuse_planes"] = min(spec.nz, c["fuse_planes"])
+    return c
 
 
 def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None, keep_u=False, launch=None,
                  in_place=False, layout=None):
     """Run warmup + timed steps; returns timing and reduction results (and
-    the final velocity field, FP64 on the device, if `keep_u`).  `launch`
-    OTHER_FORM runs two steps per launch (planes layout) instead of one."""
-    form = None
-    if launch == OTHER_FORM:
-        form = {"fuse_steps": 2, "fuse_rows": 8 if storage == "f64" else 16,
-                "fuse_planes": min(spec.nz, 32 if storage == "f64" else 8)}
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place, launch=form,
+    the final velocity field, FP64 on the device, if `keep_u`).  `launch`:
+    a launch dict (two steps per launch need the planes layout) or None."""
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place, launch=launch,
                        layout=layout)
     lat.init_rest()
     r0 = lat.reduce()
@@ -313,7 +328,10 @@ def main():
     ap.add_argument("--size", type=int, default=512, help="cavity edge length")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
     ap.add_argument("--layout", default="rows", choices=["rows", "planes"],
-                    help="state layout of the main run and the storage variants")
+                    help="state layout of the one-step runs")
+    ap.add_argument("--form", default="best", choices=["best", "one", "two"],
+                    help="launch form of the main run and the storage variants: the faster one per storage type "
+                         "(FP32 two steps per launch, FP16 and FP64 one), or one / two steps per launch for all")
     ap.add_argument("--reduce-every", type=int, default=100)
     ap.add_argument("--variant-steps", type=int, default=-1,
                     help="steps of the other storage variants (default: --steps + --warmup - 20, so that "
@@ -361,8 +379,16 @@ def main():
 
     compare = not args.no_variants and args.variant_steps < 0
     vsteps = args.steps + args.warmup - args.variant_warmup if args.variant_steps < 0 else args.variant_steps
-    main_run = time_lattice(clbm, torch, spec, args.storage, args.steps, args.warmup, args.reduce_every,
-                            keep_u=compare, layout=args.layout)
+
+    def form_of(st):
+        return BEST_FORM[st] if args.form == "best" else args.form
+
+    def run_form(st, form, steps, warmup, keep_u=False):
+        launch = launch_of(form, st, spec)
+        return time_lattice(clbm, torch, spec, st, steps, warmup, args.reduce_every, keep_u=keep_u, launch=launch,
+                            layout="planes" if launch else args.layout)
+
+    main_run = run_form(args.storage, form_of(args.storage), args.steps, args.warmup, keep_u=compare)
     mlups = spec.nodes * args.steps / (main_run["ms_per_step"] * args.steps * 1e-3) / 1e6
 
     variants = {}
@@ -371,8 +397,7 @@ def main():
         for st in ("f16", "f64", "f32"):
             if st == args.storage:
                 continue
-            r = time_lattice(clbm, torch, spec, st, vsteps, args.variant_warmup, args.reduce_every, keep_u=compare,
-                             layout=args.layout)
+            r = run_form(st, form_of(st), vsteps, args.variant_warmup, keep_u=compare)
             fields[st] = r.pop("u", None)
             spl = r["launch"]["fuse_steps"]
             variants[st] = {
@@ -386,7 +411,7 @@ def main():
     launch_forms = {}
     if not (args.no_variants or args.no_extras):
         for st in ("f32", "f64", "f16"):
-            r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, launch=OTHER_FORM)
+            r = run_form(st, "one" if form_of(st) == "two" else "two", 300, 20)
             spl = r["launch"]["fuse_steps"]
             launch_forms[st] = {
                 "launch": r["launch"], "layout": r["layout"],

@@ -221,9 +221,10 @@ typedef struct {
                             layout: bx a multiple of 64 takes the fast kernel, other widths a
                             kernel that applies the full wall rule on every lane) */
     int32_t xcd_remap;   /* 1: workgroup b takes tile (b mod 8)*(B/8) + b/8, so each of the
-                            eight XCDs sweeps a contiguous slab of the lattice */
-    int32_t nt_loads;    /* 1: non-temporal hint on population loads */
-    int32_t nt_stores;   /* 1: non-temporal hint on population stores */
+                            eight XCDs sweeps a contiguous slab of the lattice (both launch
+                            forms) */
+    int32_t nt_loads;    /* 1: non-temporal hint on population loads (one-step launch) */
+    int32_t nt_stores;   /* 1: non-temporal hint on population stores (both launch forms) */
     int32_t fuse_steps;  /* time steps per launch: 1, or 2 (temporal blocking: a workgroup
                             computes the first step on a 64 x fuse_rows patch of columns plus
                             its one-node ring, keeps it on chip and writes the second step of
@@ -245,8 +246,9 @@ clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by);
 
 /* Time one step per launch over block widths 64..512 (multiples of 64, up
  * to the lattice width rounded up to 64), 1, 2 or 4 rows per block, both tile
- * orders and both cache hints, and the two-step configuration in place if
- * fuse_steps = 2, on the current state; keep the fastest and report it and its
+ * orders and both cache hints, and, if fuse_steps = 2, the two-step
+ * configuration in place with both tile orders and both store hints, on the
+ * current state; keep the fastest and report it and its
  * time per step in ms (either output may be NULL).  The trial launches read
  * the current buffer and write the other one, so the state is unchanged; the
  * call synchronizes its stream.  Refused (EINVAL) for the one-buffer form,

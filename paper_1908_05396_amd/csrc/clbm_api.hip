@@ -240,7 +240,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     if (h->launch.fuse_steps == 2) {
         for (; t + 2 <= nsteps; t += 2) {
             HIP_TRY(launch_step2(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf,
-                                 h->forced, h->route, h->launch.fuse_rows, h->launch.fuse_planes, st),
+                                 h->forced, h->route, h->launch, st),
                     "clbm_step (two-step launch)");
             h->cur = 1 - h->cur;
             h->steps_done += 2;
@@ -387,7 +387,13 @@ clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, doub
                 cands.push_back(c);
             }
         }
-    if (h->launch.fuse_steps == 2) cands.push_back(h->launch);
+    if (h->launch.fuse_steps == 2)      // the two-step configuration in place, with both tile orders and store hints
+        for (int mode = 0; mode < 4; ++mode) {
+            StepLaunch c = h->launch;
+            c.xcd_remap = mode & 1;
+            c.nt_stores = mode >> 1;
+            cands.push_back(c);
+        }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "autotune: event");
     hipError_t e = hipEventCreate(&e1);
@@ -400,8 +406,7 @@ clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, doub
         const void *A = h->buf[h->cur];
         void *B = h->buf[1 - h->cur];
         if (c.fuse_steps == 2)
-            return launch_step2(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c.fuse_rows,
-                                c.fuse_planes, st);
+            return launch_step2(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c, st);
         if (h->geom.rows)
             return launch_step_rows(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c, st);
         return launch_step(h->prm.storage, A, B, h->geom, h->rd, h->rf, h->forced, h->route, c, st);

@@ -71,9 +71,12 @@ template <typename S, typename T> __device__ inline T round_trip(T v) {
 struct FusedGrid {
     uint32_t gx, gy, gz;    // patches along x and y, z chunks
     int32_t cz;             // output planes per z chunk
+    uint32_t aligned;       // largest multiple of 8 <= number of workgroups
+    int32_t remap;          // XCD-contiguous patch order
 };
 
-template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF>
+// StAux: cache hint of the population stores (0 plain, 2 non-temporal)
+template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF, int StAux>
 __global__ void __launch_bounds__(kLanes * ROWS)
 stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, FusedGrid L) {
     __shared__ FusedShared<S, ROWS> sh;
@@ -81,6 +84,10 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
     const int l = (int)(threadIdx.x & (kLanes - 1));
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kLanes));
     uint32_t b = blockIdx.x;
+    // XCD-contiguous order: workgroups b, b + 8, ... share an XCD (and its L2),
+    // so they take neighbouring patches, whose halos and partly written cache
+    // lines then meet in the same cache
+    if (L.remap && b < L.aligned) b = (b & 7u) * (L.aligned >> 3) + (b >> 3);
     const int tx = (int)(b % L.gx);
     b /= L.gx;
     const int ty = (int)(b % L.gy);
@@ -215,7 +222,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
         asm volatile("" : "+s"(Bz));
         const uint32_t self = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy + (uint32_t)g.nxy * (uint32_t)z;
 #pragma unroll
-        for (int a = 0; a < Q; ++a) Plane<S, 2>::store(Bz, g, a, self, d[a]);
+        for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(Bz, g, a, self, d[a]);
     };
 
     // plane m = z0 - 1 .. z1: first step of I(m), then the output plane m - 1
@@ -243,44 +250,52 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
 }
 
 template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF>
-static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T> &p, int planes, hipStream_t st) {
+static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
+                            hipStream_t st) {
     FusedGrid L;
     L.gx = (uint32_t)((g.nx + kOut - 1) / kOut);
     L.gy = (uint32_t)((g.ny + ROWS - 3) / (ROWS - 2));
-    L.cz = planes;
-    L.gz = (uint32_t)((g.nz + planes - 1) / planes);
+    L.cz = c.fuse_planes;
+    L.gz = (uint32_t)((g.nz + c.fuse_planes - 1) / c.fuse_planes);
     const uint64_t nb = (uint64_t)L.gx * L.gy * L.gz;
     if (nb == 0 || nb > 0x7fffffffull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF>), dim3((uint32_t)nb), dim3(kLanes * ROWS),
-                       0, st, (const S *)A, (S *)B, g, p, L);
+    L.aligned = (uint32_t)nb & ~7u;
+    L.remap = c.xcd_remap;
+    if (c.nt_stores)
+        hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF, 2>), dim3((uint32_t)nb),
+                           dim3(kLanes * ROWS), 0, st, (const S *)A, (S *)B, g, p, L);
+    else
+        hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF, 0>), dim3((uint32_t)nb),
+                           dim3(kLanes * ROWS), 0, st, (const S *)A, (S *)B, g, p, L);
     return hipGetLastError();
 }
 
 template <typename S, typename T, int ROWS, bool PF = false>
 static hipError_t launch2_r(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
-                            int planes, hipStream_t st) {
+                            const StepLaunch &c, hipStream_t st) {
     if (route == 0)
-        return forced ? launch2_f<S, T, true, 0, ROWS, PF>(A, B, g, p, planes, st)
-                      : launch2_f<S, T, false, 0, ROWS, PF>(A, B, g, p, planes, st);
-    return forced ? launch2_f<S, T, true, 1, ROWS, PF>(A, B, g, p, planes, st)
-                  : launch2_f<S, T, false, 1, ROWS, PF>(A, B, g, p, planes, st);
+        return forced ? launch2_f<S, T, true, 0, ROWS, PF>(A, B, g, p, c, st)
+                      : launch2_f<S, T, false, 0, ROWS, PF>(A, B, g, p, c, st);
+    return forced ? launch2_f<S, T, true, 1, ROWS, PF>(A, B, g, p, c, st)
+                  : launch2_f<S, T, false, 1, ROWS, PF>(A, B, g, p, c, st);
 }
 
 hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
-                        const Relax<float> &pf, bool forced, int route, int rows, int planes, hipStream_t st) {
-    if (planes < 1 || route == 2) return hipErrorInvalidValue;   // no two-step form of the BGK model
+                        const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st) {
+    if (c.fuse_planes < 1 || route == 2) return hipErrorInvalidValue;   // no two-step form of the BGK model
+    const int rows = c.fuse_rows;
     switch (storage) {
     case 0:
         if (rows != 8) return hipErrorInvalidValue;
-        return launch2_r<double, double, 8>(A, B, g, pd, forced, route, planes, st);
+        return launch2_r<double, double, 8>(A, B, g, pd, forced, route, c, st);
     case 1:
         // rows 12: the next plane's loads go straight to LDS (153 KiB in all)
-        return rows == 16 ? launch2_r<float, float, 16>(A, B, g, pf, forced, route, planes, st)
-             : rows == 12 ? launch2_r<float, float, 12, true>(A, B, g, pf, forced, route, planes, st)
-                          : launch2_r<float, float, 8>(A, B, g, pf, forced, route, planes, st);
+        return rows == 16 ? launch2_r<float, float, 16>(A, B, g, pf, forced, route, c, st)
+             : rows == 12 ? launch2_r<float, float, 12, true>(A, B, g, pf, forced, route, c, st)
+                          : launch2_r<float, float, 8>(A, B, g, pf, forced, route, c, st);
     default:
-        return rows == 16 ? launch2_r<__half, float, 16>(A, B, g, pf, forced, route, planes, st)
-                          : launch2_r<__half, float, 8>(A, B, g, pf, forced, route, planes, st);
+        return rows == 16 ? launch2_r<__half, float, 16>(A, B, g, pf, forced, route, c, st)
+                          : launch2_r<__half, float, 8>(A, B, g, pf, forced, route, c, st);
     }
 }
 

@@ -37,7 +37,7 @@ hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const
 hipError_t launch_step_rows(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                             const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
 hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
-                        const Relax<float> &pf, bool forced, int route, int rows, int planes, hipStream_t st);
+                        const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
 hipError_t launch_aa_pair(int storage, void *A, const Geom &g, const Relax<double> &pd, const Relax<float> &pf,
                           bool forced, int route, const StepLaunch &c, hipStream_t st);
 hipError_t launch_store_plain(int storage, const double *f0, void *A, const Geom &g, hipStream_t st);

@@ -57,12 +57,20 @@ def _oracle_at(spec, seed, eps, pt, k):
 @pytest.mark.parametrize("config,storage,layout", [
     ("cavity512", "f32", "rows"), ("cavity512", "f16", "rows"), ("cavity512", "f64", "rows"),
     ("cavity512", "f32", "planes"), ("cavity512", "f16", "planes"), ("cavity256", "f32", "rows"),
-    ("cavity256", "f16", "rows")])
+    ("cavity256", "f16", "rows"), ("cavity512", "f32", "two-step"), ("cavity512", "f64", "two-step")])
 def test_light_cone_samples(clbm, config, storage, layout):
+    """layout "two-step": the planes layout with the two-steps-per-launch
+    configuration that bench.py times for this storage type (K_STEPS is even:
+    two-step launches only)."""
+    from bench import TWO_STEP
     spec = W.config_cavity512() if config == "cavity512" else W.config_cavity256()
     seed, eps = 77, 2e-3
     print(f"[gpu] full-size {spec.name} {storage} {layout} k={K_STEPS}", flush=True)
-    lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
+    if layout == "two-step":
+        lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout="planes", launch=TWO_STEP[storage])
+        assert lat.get_launch()["fuse_steps"] == 2 and K_STEPS % 2 == 0
+    else:
+        lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
     f0 = W.perturbed_populations(spec, seed, eps, device="cuda")
     lat.init_populations(f0)
     del f0

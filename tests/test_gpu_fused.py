@@ -85,6 +85,25 @@ def test_two_step_equals_one_step(clbm, geom, storage, rows):
         assert diff <= bound, f"{geom} {storage} rows={rows} planes={planes}: max diff {diff}"
 
 
+@pytest.mark.parametrize("storage,rows", [("f32", 16), ("f32", 12), ("f16", 8), ("f64", 8)])
+def test_two_step_tile_order_and_store_hint(clbm, storage, rows):
+    """The XCD-contiguous patch order and the store hint change only where and
+    how each output is written: every combination gives the same bits.  With
+    16 rows the lattice has 36 patches (3 x 3 x 4) and with 8 rows 84, so the
+    remapped range (a multiple of 8) and a remainder left in dispatch order
+    both occur."""
+    spec = _geometries()["multi_patch"]
+    outs = []
+    for mode in range(4):
+        launch = {"fuse_steps": 2, "fuse_rows": rows, "fuse_planes": 3, "xcd_remap": mode & 1,
+                  "nt_stores": mode >> 1}
+        print(f"[gpu] fused order/hint {storage} rows={rows} {launch}", flush=True)
+        st, _ = _run(clbm, spec, storage, 6, launch)
+        outs.append(st.cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_two_step_printed_moment_form(clbm, storage):
     spec = W.cavity(20, 0.05, 0.8, 100.0).with_(omega_bulk=1.2, omega_high=(1.1, 0.9, 1.3, 1.0, 1.2, 0.8, 1.1, 1.4, 0.95))
