@@ -90,7 +90,7 @@ typedef enum {
  * and give the same results; the row layout keeps the 19 populations of a row
  * within 19*nx consecutive values, so one step reads 9 and writes 1 compact
  * region per row instead of touching 38 planes far apart in memory, which
- * DRAM serves faster.  Two steps per launch need planes. */
+ * DRAM serves faster.  Both run one or two steps per launch. */
 typedef enum {
     CLBM_LAYOUT_PLANES = 0,
     CLBM_LAYOUT_ROWS = 1
@@ -230,9 +230,10 @@ typedef struct {
                             its one-node ring, keeps it on chip and writes the second step of
                             the inner 62 x (fuse_rows - 2) columns, marching along z; the
                             result equals two one-step launches).  clbm_step runs an odd
-                            remainder as one one-step launch.  Planes layout only */
+                            remainder as one one-step launch.  Either layout (not the
+                            one-buffer form) */
     int32_t fuse_rows;   /* rows of a two-step workgroup, ring included: 8, 16 (not FP64), or
-                            12 (FP32: the next plane's loads go straight to LDS) */
+                            12 (FP32; planes layout: the next plane's loads go straight to LDS) */
     int32_t fuse_planes; /* output z planes per two-step workgroup, >= 1 */
     int32_t reserved;    /* must be 0 */
 } clbm_launch;

@@ -324,8 +324,6 @@ clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
     if (!rows_ok) return fail(CLBM_EINVAL, "fuse_rows must be 8, 16 (not FP64) or 12 (FP32 only)");
     if (c->fuse_planes < 1) return fail(CLBM_EINVAL, "fuse_planes must be >= 1");
     if (c->fuse_steps == 2 && h->in_place) return fail(CLBM_EINVAL, "in-place lattices run one step per launch");
-    if (c->fuse_steps == 2 && h->geom.rows)
-        return fail(CLBM_EINVAL, "two steps per launch need the planes layout");
     if (c->fuse_steps == 2 && h->route == 2)
         return fail(CLBM_EINVAL, "the single-relaxation-time model runs one step per launch");
     if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");

@@ -23,7 +23,12 @@
 // the bounce-back of the output plane at its own height.  With one barrier per
 // plane, a slot read while producing output z is rewritten no earlier than
 // while producing z + 2, which the ring sizes guarantee.
-#include "clbm_internal.hpp"
+//
+// Either state layout: in the row layout a wave's first-step row and output
+// row are lattice rows, so its loads and stores go through the one-step row
+// kernel's gather and store (scalar row bases, one lane offset); in the planes
+// layout through the per-plane gather.
+#include "clbm_rows.hpp"
 
 namespace clbm {
 
@@ -75,10 +80,12 @@ struct FusedGrid {
     int32_t remap;          // XCD-contiguous patch order
 };
 
-// StAux: cache hint of the population stores (0 plain, 2 non-temporal)
-template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF, int StAux>
+// StAux: cache hint of the population stores (0 plain, 2 non-temporal);
+// Rows: row layout (else planes)
+template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF, int StAux, bool Rows>
 __global__ void __launch_bounds__(kLanes * ROWS)
 stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<T> p, FusedGrid L) {
+    static_assert(!(Rows && PF), "the direct-to-LDS prefetch reads the planes layout");
     __shared__ FusedShared<S, ROWS> sh;
     __shared__ FusedInput<S, ROWS, PF> pf;
     const int l = (int)(threadIdx.x & (kLanes - 1));
@@ -146,7 +153,13 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
         if constexpr (PF) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // this wave's prefetch has landed
         if (v) {
             const uint32_t self = (uint32_t)wx + (uint32_t)g.nx * (uint32_t)wy + (uint32_t)g.nxy * (uint32_t)wz;
-            if constexpr (PF) {
+            if constexpr (Rows) {
+                // the wave's row (wy, wz) is uniform: off the y and z faces, or on one
+                if (wy >= 1 && wy <= g.ny - 2 && wz >= 1 && wz <= g.nz - 2)
+                    row_gather<S, T, 0, false>(A, g, p, wx, wy, wz, d);
+                else
+                    row_gather<S, T, 0, true>(A, g, p, wx, wy, wz, d);
+            } else if constexpr (PF) {
 #pragma unroll
                 for (int a = 0; a < Q; ++a) d[a] = Conv<S, T>::load(pf.in[a][w][l]);
                 fix_edges<S, T>(Am, g, p, wx, wy, wz, self, d);
@@ -218,11 +231,15 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
             }
         }
         collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
-        S *Bz = B;
-        asm volatile("" : "+s"(Bz));
-        const uint32_t self = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy + (uint32_t)g.nxy * (uint32_t)z;
+        if constexpr (Rows) {
+            row_store<S, T, StAux>(B, g, gx, gy, z, d);
+        } else {
+            S *Bz = B;
+            asm volatile("" : "+s"(Bz));
+            const uint32_t self = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy + (uint32_t)g.nxy * (uint32_t)z;
 #pragma unroll
-        for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(Bz, g, a, self, d[a]);
+            for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(Bz, g, a, self, d[a]);
+        }
     };
 
     // plane m = z0 - 1 .. z1: first step of I(m), then the output plane m - 1
@@ -249,7 +266,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
     }
 }
 
-template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF>
+template <typename S, typename T, bool Forced, int Route, int ROWS, bool PF, bool Rows>
 static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T> &p, const StepLaunch &c,
                             hipStream_t st) {
     FusedGrid L;
@@ -262,22 +279,30 @@ static hipError_t launch2_f(const void *A, void *B, const Geom &g, const Relax<T
     L.aligned = (uint32_t)nb & ~7u;
     L.remap = c.xcd_remap;
     if (c.nt_stores)
-        hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF, 2>), dim3((uint32_t)nb),
+        hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF, 2, Rows>), dim3((uint32_t)nb),
                            dim3(kLanes * ROWS), 0, st, (const S *)A, (S *)B, g, p, L);
     else
-        hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF, 0>), dim3((uint32_t)nb),
+        hipLaunchKernelGGL((stream_collide2_kernel<S, T, Forced, Route, ROWS, PF, 0, Rows>), dim3((uint32_t)nb),
                            dim3(kLanes * ROWS), 0, st, (const S *)A, (S *)B, g, p, L);
     return hipGetLastError();
 }
 
+template <typename S, typename T, int ROWS, bool PF, bool Rows>
+static hipError_t launch2_l(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
+                            const StepLaunch &c, hipStream_t st) {
+    if (route == 0)
+        return forced ? launch2_f<S, T, true, 0, ROWS, PF, Rows>(A, B, g, p, c, st)
+                      : launch2_f<S, T, false, 0, ROWS, PF, Rows>(A, B, g, p, c, st);
+    return forced ? launch2_f<S, T, true, 1, ROWS, PF, Rows>(A, B, g, p, c, st)
+                  : launch2_f<S, T, false, 1, ROWS, PF, Rows>(A, B, g, p, c, st);
+}
+
+// row layout: no direct-to-LDS prefetch (ROWS 12 runs without it)
 template <typename S, typename T, int ROWS, bool PF = false>
 static hipError_t launch2_r(const void *A, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
                             const StepLaunch &c, hipStream_t st) {
-    if (route == 0)
-        return forced ? launch2_f<S, T, true, 0, ROWS, PF>(A, B, g, p, c, st)
-                      : launch2_f<S, T, false, 0, ROWS, PF>(A, B, g, p, c, st);
-    return forced ? launch2_f<S, T, true, 1, ROWS, PF>(A, B, g, p, c, st)
-                  : launch2_f<S, T, false, 1, ROWS, PF>(A, B, g, p, c, st);
+    return g.rows ? launch2_l<S, T, ROWS, false, true>(A, B, g, p, forced, route, c, st)
+                  : launch2_l<S, T, ROWS, PF, false>(A, B, g, p, forced, route, c, st);
 }
 
 hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,

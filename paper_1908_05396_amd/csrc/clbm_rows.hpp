@@ -82,11 +82,11 @@ inline RowLaunch row_launch(const Geom &g, int bx, int by, int remap) {
     return L;
 }
 
-// Node x of row (y, z), y and z uniform over the wave; Face: the row lies on
-// a y or z face.
-template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face>
-__device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p, int x,
-                                int y, int z) {
+// Pull of node x of row (y, z) with the wall rules into d; y and z uniform
+// over the wave; Face: the row lies on a y or z face.
+template <typename S, typename T, int LdAux, bool Face>
+__device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
+                                  T (&d)[Q]) {
     constexpr uint32_t es = sizeof(S);
     const int64_t r = (int64_t)z * g.ny + y;
     // Each direction reads a run of its source row through a base one value
@@ -111,7 +111,6 @@ __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, cons
     auto own = [&](int a) {
         return (T)RawBits<S>::template load<LdAux>(own_rsrc, (uint32_t)(opp(a) * g.nx + x) * es);
     };
-    T d[Q];
     if constexpr (!Face) {
 #pragma unroll
         for (int a = 0; a < Q; ++a)
@@ -150,13 +149,28 @@ __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, cons
             d[a] = wall_value<T>(own(a), p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
         }
     }
-    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+}
+
+// Store of the 19 populations of node x of row (y, z) (y, z uniform).
+template <typename S, typename T, int StAux>
+__device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y, int z, const T (&d)[Q]) {
+    constexpr uint32_t es = sizeof(S);
     const uint32_t srange = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
-    S *out = B + r * g.row;
+    S *out = B + ((int64_t)z * g.ny + y) * g.row;
     const uint32_t lane = (uint32_t)x * es;
 #pragma unroll
     for (int a = 0; a < Q; ++a)
         RawBits<S>::template store<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a]);
+}
+
+// One step of node x of row (y, z): gather, collide, store.
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face>
+__device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p, int x,
+                                int y, int z) {
+    T d[Q];
+    row_gather<S, T, LdAux, Face>(A, g, p, x, y, z, d);
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    row_store<S, T, StAux>(B, g, x, y, z, d);
 }
 
 }  // namespace clbm
