@@ -247,9 +247,10 @@ clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by);
 
 /* Time one step per launch over block widths 64..512 (multiples of 64, up
  * to the lattice width rounded up to 64), 1, 2 or 4 rows per block, both tile
- * orders and both cache hints, and, if fuse_steps = 2, the two-step
- * configuration in place with both tile orders and both store hints, on the
- * current state; keep the fastest and report it and its
+ * orders and both cache hints, and two steps per launch over patch heights 8
+ * and 16 (8 only for FP64), z chunks of 16 and 32 planes, both patch orders
+ * and both store hints (not for the single-relaxation-time model), plus the
+ * two-step configuration in place if fuse_steps = 2, on the current state; keep the fastest and report it and its
  * time per step in ms (either output may be NULL).  The trial launches read
  * the current buffer and write the other one, so the state is unchanged; the
  * call synchronizes its stream.  Refused (EINVAL) for the one-buffer form,

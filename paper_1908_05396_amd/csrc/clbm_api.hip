@@ -385,13 +385,24 @@ clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, doub
                 cands.push_back(c);
             }
         }
-    if (h->launch.fuse_steps == 2)      // the two-step configuration in place, with both tile orders and store hints
-        for (int mode = 0; mode < 4; ++mode) {
-            StepLaunch c = h->launch;
-            c.xcd_remap = mode & 1;
-            c.nt_stores = mode >> 1;
-            cands.push_back(c);
+    // two steps per launch (not for the comparison model): patch heights 8 and 16 (not FP64), z chunks of 16
+    // and 32 planes, both patch orders and store hints
+    if (h->route != 2)
+        for (int rows = 8; rows <= 16; rows += 8) {
+            if (rows == 16 && h->prm.storage == CLBM_F64) continue;
+            for (int planes = 16; planes <= 32; planes *= 2)
+                for (int mode = 0; mode < 4; ++mode) {
+                    StepLaunch c = h->launch;
+                    c.fuse_steps = 2;
+                    c.fuse_rows = rows;
+                    c.fuse_planes = planes;
+                    c.xcd_remap = mode & 1;
+                    c.nt_stores = mode >> 1;
+                    cands.push_back(c);
+                }
         }
+    if (h->launch.fuse_steps == 2)      // the two-step configuration in place
+        cands.push_back(h->launch);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "autotune: event");
     hipError_t e = hipEventCreate(&e1);
