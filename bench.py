@@ -357,7 +357,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's "
-                                   "multi-GPU decomposition is not part of this build",
+                                   "multi-GPU decomposition (z slabs with ghost planes) is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

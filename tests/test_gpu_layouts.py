@@ -120,18 +120,19 @@ def test_rows_rest_state_and_reductions(clbm):
         assert abs(r1[k] - r2[k]) <= 1e-12 * max(1.0, abs(r2[k])), k
 
 
-@pytest.mark.parametrize("layout", ["rows", "planes"])
-def test_autotune_keeps_state_and_results(clbm, layout):
+@pytest.mark.parametrize("layout,storage", [("rows", "f32"), ("planes", "f32"), ("rows", "f64")])
+def test_autotune_keeps_state_and_results(clbm, layout, storage):
     """clbm_autotune times launches into the spare buffer: the state is
     unchanged, and stepping with the chosen launch gives the same bits as the
     default launch (one step per launch), or the same values to rounding (two
     steps per launch: the two inlined collisions may contract multiply-adds
     differently)."""
     spec = _geometries()["lid_py_130x12x9"]
-    print(f"[gpu] autotune {layout}", flush=True)
+    print(f"[gpu] autotune {layout} {storage}", flush=True)
+    tol = {"f32": 1e-6, "f64": 1e-14}[storage]      # two vs one step per launch: rounding only
     outs = []
     for tune in (False, True):
-        lat = clbm.Lattice(spec, storage="f32", track_residual=False, layout=layout)
+        lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
         lat.init_populations(W.perturbed_populations(spec, 12, 1e-2, device="cuda"))
         lat.step(3)
         if tune:
@@ -147,15 +148,16 @@ def test_autotune_keeps_state_and_results(clbm, layout):
     if cfg["fuse_steps"] == 1:
         assert np.array_equal(outs[0], outs[1])
     else:
-        assert np.abs(outs[0] - outs[1]).max() <= 1e-6
-    # the two-step candidates alone, on the same lattice, as the autotuner would run them
-    lat = clbm.Lattice(spec, storage="f32", track_residual=False, layout=layout,
-                       launch={"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0})
+        assert np.abs(outs[0] - outs[1]).max() <= tol
+    # a two-step candidate alone, on the same lattice, as the autotuner would run it
+    rows = 16 if storage != "f64" else 8
+    lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout,
+                       launch={"fuse_steps": 2, "fuse_rows": rows, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0})
     lat.init_populations(W.perturbed_populations(spec, 12, 1e-2, device="cuda"))
     lat.step(9)
-    assert np.abs(lat.populations().cpu().numpy() - outs[0]).max() <= 1e-6
+    assert np.abs(lat.populations().cpu().numpy() - outs[0]).max() <= tol
     lat.close()
-    ip = clbm.Lattice(spec, storage="f32", in_place=True, layout=layout)
+    ip = clbm.Lattice(spec, storage=storage, in_place=True, layout=layout)
     ip.init_rest()
     with pytest.raises(clbm.ClbmError):
         ip.autotune()
