@@ -179,10 +179,14 @@ def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch, lay
     measured HBM bytes per launch from the committed counter summary."""
     achieved = BYTES_PER_LUP[storage] * nodes / (kernel_ms_per_step * 1e-3) / 1e9
     kernel = STEP_KERNEL[layout] if steps_per_launch == 1 else "stream_collide2"
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(storage, workload, kernel), "kernel": kernel,
-            "bytes_per_lup": BYTES_PER_LUP[storage], "steps_per_launch": steps_per_launch}
+    traffic = measured_traffic(storage, workload, kernel)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+           "bytes_per_lup": BYTES_PER_LUP[storage], "steps_per_launch": steps_per_launch}
+    if traffic is not None:
+        # measured HBM bytes over the algorithmic bytes of one launch (below 1: temporal blocking)
+        out["traffic_over_algorithmic"] = round(traffic / (BYTES_PER_LUP[storage] * nodes * steps_per_launch), 3)
+    return out
 
 
 def batched(clbm, torch, W, storage, steps):
