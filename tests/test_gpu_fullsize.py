@@ -57,17 +57,20 @@ def _oracle_at(spec, seed, eps, pt, k):
 @pytest.mark.parametrize("config,storage,layout", [
     ("cavity512", "f32", "rows"), ("cavity512", "f16", "rows"), ("cavity512", "f64", "rows"),
     ("cavity512", "f32", "planes"), ("cavity512", "f16", "planes"), ("cavity256", "f32", "rows"),
-    ("cavity256", "f16", "rows"), ("cavity512", "f32", "two-step"), ("cavity512", "f64", "two-step")])
+    ("cavity256", "f16", "rows"), ("cavity512", "f32", "two-step"), ("cavity512", "f64", "two-step"),
+    ("cavity512", "f32", "two-step-rows")])
 def test_light_cone_samples(clbm, config, storage, layout):
     """layout "two-step": the planes layout with the two-steps-per-launch
-    configuration that bench.py times for this storage type (K_STEPS is even:
-    two-step launches only)."""
+    configuration that bench.py times for this storage type; "two-step-rows":
+    the same configuration in the row layout (the autotuner's pick for the
+    row-layout lattice).  K_STEPS is even: two-step launches only."""
     from bench import TWO_STEP
     spec = W.config_cavity512() if config == "cavity512" else W.config_cavity256()
     seed, eps = 77, 2e-3
     print(f"[gpu] full-size {spec.name} {storage} {layout} k={K_STEPS}", flush=True)
-    if layout == "two-step":
-        lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout="planes", launch=TWO_STEP[storage])
+    if layout.startswith("two-step"):
+        lat = clbm.Lattice(spec, storage=storage, track_residual=False,
+                           layout="rows" if layout.endswith("rows") else "planes", launch=TWO_STEP[storage])
         assert lat.get_launch()["fuse_steps"] == 2 and K_STEPS % 2 == 0
     else:
         lat = clbm.Lattice(spec, storage=storage, track_residual=False, layout=layout)
