@@ -85,3 +85,24 @@ def test_zero_steps_change_nothing(clbm, form):
     for i in range(2):
         assert np.array_equal(before[i], b.populations(i).cpu().numpy())
     b.close()
+
+
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_degenerate_instances_in_a_batch(clbm, layout):
+    """The same lattices as instances of one batch (persistent launch, graph
+    replay), beside an ordinary one."""
+    specs = list(_specs().values()) + [W.cavity(12, 0.05, 0.9, 50.0, name="b12")]
+    steps, eps = 6, 1e-2
+    b = clbm.Batch(specs, storage="f64", layout=layout)
+    b.init_rest()
+    for i, sp in enumerate(specs):
+        b.init_populations(i, W.perturbed_populations(sp, 20 + i, eps, device="cuda"))
+    b.set_config(graph_steps=4)
+    b.step(steps)
+    for i, sp in enumerate(specs):
+        f = b.populations(i).cpu().numpy()
+        ref = oracle.collide(sp, oracle.run(sp, W.perturbed_populations(sp, 20 + i, eps).numpy(), steps))
+        err = np.abs(f - ref).max()
+        print(f"[gpu] batch {layout} {sp.name}: {err:.3e}", flush=True)
+        assert err < TOL_F["f64"], (sp.name, err)
+    b.close()
