@@ -34,10 +34,10 @@
  *     weight w = (1/3, 1/18 x 6, 1/36 x 12), stored as double (CLBM_F64),
  *     float (CLBM_F32) or IEEE half (CLBM_F16_DEV, round to nearest even).
  *     Arithmetic is double for CLBM_F64 and float otherwise.
- *   - All device pointers must be 256-byte aligned device memory owned by
- *     the caller.  The library never frees caller memory.  It allocates a
+ *   - State buffers and pools must be 256-byte aligned device memory owned
+ *     by the caller.  The library never frees caller memory.  It allocates a
  *     small amount of its own device memory in clbm_create (reduction
- *     partials, an optional velocity snapshot) and none in clbm_step.
+ *     partials, an optional FP64 velocity snapshot) and none in clbm_step.
  *   - Streams are hipStream_t values passed as void* (0 = null stream).
  *     clbm_step and the other launches are asynchronous; clbm_reduce
  *     synchronizes its stream.
@@ -101,6 +101,12 @@ typedef enum {
     CLBM_LID_PY = 4, CLBM_LID_MZ = 5, CLBM_LID_PZ = 6
 } clbm_lid_face;
 
+/* Per-node flag values of the optional flag array of clbm_create: a fluid
+ * node is updated by the scheme; a link from a fluid node to a wall node is
+ * closed by half-way bounce-back (Sec. 4.1), and to a moving-wall node by
+ * bounce-back with the moving-wall momentum term of lid_velocity (Sec. 4.3). */
+enum { CLBM_FLUID = 0, CLBM_WALL = 1, CLBM_MOVING_WALL = 2 };
+
 /* Problem description (Sec. 2 constitutive law, Sec. 3 scheme, Sec. 4 set-ups).
  * Fill with clbm_params_default() and override. */
 typedef struct {
@@ -111,7 +117,8 @@ typedef struct {
     int32_t storage;           /* clbm_storage */
     int32_t attractor_literal; /* 0: fourth-order attractors kxx*kyy/rho (default);
                                   1: kxx*kyy as printed (linearly unstable, for study only) */
-    int32_t track_residual;    /* 1: keep a velocity snapshot for the steady-state residual */
+    int32_t track_residual;    /* 1: keep an FP64 velocity snapshot (24 bytes per node) for the
+                                  steady-state residual of clbm_reduce; 0: no residual */
     int32_t plane_pad;         /* planes layout: extra elements between population planes (>= 0), on
                                   top of the 256-byte rounding; -1: library default (see
                                   clbm_buffer_size); unused in the row layout */
@@ -138,7 +145,8 @@ typedef struct clbm_lattice clbm_lattice;
 /* Defaults: 1x1x1, no periodic axis, no lid, FP32 storage, normalized
  * attractors, residual tracking on, default plane padding, automatic
  * collision form, row layout, K = 0.01, n = 1, viscosity clip for omega in [0.1, 1.95],
- * omega_bulk = omega_high = 1, no force, rho_wall = 1. */
+ * omega_bulk = omega_high = 1 (the paper's choice, Sec. 3.2), no force,
+ * rho_wall = 1.  EINVAL if p is NULL. */
 clbm_status clbm_params_default(clbm_params *p);
 
 /* Element stride between the values of populations alpha and alpha + 1 of
@@ -147,15 +155,31 @@ clbm_status clbm_params_default(clbm_params *p);
  * 256 bytes more when the rounded plane is a multiple of 64 KiB, so the 19
  * planes do not all start on the same HBM channel); the buffer holds 19
  * planes.  Rows: the stride is nx and the buffer holds 19*nx*ny*nz values
- * (plane_pad unused).  Either output pointer may be NULL. */
+ * (plane_pad unused).  Either output pointer may be NULL.  Validates the
+ * parameters (EINVAL). */
 clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane_stride, size_t *bytes);
 
-/* Create a lattice over two caller-owned state buffers of `bytes_each` bytes
- * (>= clbm_buffer_size), 256-byte aligned.  Validates every parameter
- * (EINVAL), allocates reduction scratch (ENOMEM/EHIP).  The state is
+/* Create a lattice (the problem statement of Sec. 4: dimensions, power law
+ * K and n of Eq. 5, body force or lid velocity, wall kinds) over two
+ * caller-owned state buffers of `bytes_each` bytes (>= clbm_buffer_size),
+ * 256-byte aligned device memory.
+ *
+ * flags: NULL, or a device array of nx*ny*nz bytes (node index
+ * x + nx*(y + ny*z)) of CLBM_FLUID / CLBM_WALL / CLBM_MOVING_WALL, owned by
+ * the caller, read by every step and left unchanged for the lifetime of the
+ * lattice.  NULL gives the box of the parameters (walls, lid and periodic
+ * axes on its faces, the geometry of every set-up of Sec. 4) and the tuned
+ * kernels.  With flags, solid nodes are inside the lattice (the box faces
+ * still follow the parameters), hold the rest state, report rho = 1 and
+ * u = 0, and are left out of clbm_reduce; such lattices run one generic
+ * kernel, one step per launch (fuse_steps = 2 and clbm_autotune are refused).
+ *
+ * Validates every parameter and flag value (EINVAL, with the reason in
+ * clbm_last_error), allocates reduction scratch (ENOMEM/EHIP).  With flags
+ * the call synchronizes the null stream once (flag check).  The state is
  * undefined until an init call. */
 clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each,
-                        clbm_lattice **out);
+                        const uint8_t *flags, clbm_lattice **out);
 
 /* Create a lattice over ONE caller-owned state buffer (half the memory of
  * clbm_create), stepped in place with the AA access pattern: an even step
@@ -167,42 +191,61 @@ clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t b
  * (time t, before its collision), so clbm_populations returns those;
  * clbm_init_* store the initial populations without colliding them;
  * clbm_step accepts even step counts only (EINVAL otherwise); one step per
- * launch (fuse_steps = 2 is refused); either layout.  Velocities from clbm_macroscopic and
- * clbm_reduce are the same physical quantities as in the two-buffer form. */
+ * launch (fuse_steps = 2 is refused); either layout; no per-node flags.
+ * Velocities from clbm_macroscopic and clbm_reduce are the same physical
+ * quantities as in the two-buffer form.  The streaming and collision are
+ * those of clbm_step (Sec. 3); the access pattern is the published "AA"
+ * scheme for single-buffer lattice Boltzmann updates (Bailey et al., ICPP
+ * 2009). */
 clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out);
 
-/* Rest initial state f = w (rho = 1, u = 0), collided once so the buffer
- * holds post-collision populations (time 0; stored as is in the in-place
- * form). */
+/* Rest initial state f = w (rho = 1, u = 0; the rest state of the
+ * attractors of Sec. 3), collided once so the buffer holds post-collision
+ * populations (time 0; stored as is in the in-place form).  Asynchronous. */
 clbm_status clbm_init_rest(clbm_lattice *h, void *stream);
 
-/* Initial state from caller populations f0 (device memory, double, 19
- * planes of nx*ny*nz values, unpadded, alpha-major): collided once and stored
- * in the state's format (the in-place form stores f0 itself).  f0 is only
- * read. */
-clbm_status clbm_init_populations(clbm_lattice *h, const double *f0_dev, void *stream);
+/* Initial state from caller populations f0 (double, 19 planes of
+ * nx*ny*nz values, unpadded, alpha-major, in the velocity order of Sec. 3):
+ * collided once (Eq. cascaded collision) and stored in the state's format
+ * (the in-place form stores f0 itself).  f0 is only read.  on_device = 1:
+ * f0 is device memory and the call is asynchronous (f0 must stay valid until
+ * `stream` has run it); on_device = 0: f0 is host memory, which the call
+ * copies through a temporary device buffer (ENOMEM/EHIP if that allocation
+ * fails) and then synchronizes `stream`.  Other values: EINVAL. */
+clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, int on_device, void *stream);
 
-/* Advance nsteps time steps (>= 0): one fused pull stream-collide launch per
- * step (two steps per launch with fuse_steps = 2; in the in-place form one
- * launch per step and nsteps even).  Asynchronous; no host synchronization. */
+/* Advance nsteps time steps (>= 0; Sec. 3: collision, Eq. cascaded
+ * collision with the local relaxation rate of Sec. 3.2, then streaming,
+ * Eq. cascaded streaming, with the wall rules of Sec. 4): one fused pull
+ * stream-collide launch per step (two steps per launch with fuse_steps = 2;
+ * in the in-place form one launch per step and nsteps even).  Asynchronous;
+ * no host synchronization, no allocation, no NaN check (clbm_reduce does
+ * that).  EINVAL for nsteps < 0, ESTATE before an init call. */
 clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream);
 
-/* Density and velocity at the current time (device outputs, double,
- * unpadded): rho[i], u[c*N + i] for c = x, y, z.  Collision conserves mass
- * and momentum, so they are read from the stored post-collision populations:
- * rho = sum f, u = (sum e f - F/2)/rho (in-place form, pre-collision
- * populations: u = (sum e f + F/2)/rho).  Either pointer may be NULL. */
-clbm_status clbm_macroscopic(clbm_lattice *h, double *rho_dev, double *u_dev, void *stream);
+/* Density and velocity at the current time (the hydrodynamic fields of
+ * Sec. 3, Eq. hydrodynamic fields), computed in FP64 and written to device
+ * outputs in out_prec (CLBM_F64: double, CLBM_F32: float; CLBM_F16_DEV is
+ * refused with EINVAL), unpadded: rho[i], u[c*N + i] for c = x, y, z.
+ * Collision conserves mass and momentum, so they are read from the stored
+ * post-collision populations: rho = sum f, u = (sum e f - F/2)/rho (in-place
+ * form, pre-collision populations: u = (sum e f + F/2)/rho).  Solid nodes of
+ * a flagged lattice report rho = 1, u = 0.  Either pointer may be NULL.
+ * Asynchronous. */
+clbm_status clbm_macroscopic(clbm_lattice *h, void *rho_dev, void *u_dev, int32_t out_prec, void *stream);
 
-/* The stored populations f = w + stored deviation, as double, 19 unpadded
- * planes (device output): post-collision, or pre-collision in the in-place
- * form. */
+/* The stored populations f = w + stored deviation (Sec. 3 velocity order),
+ * as double, 19 unpadded planes (device output, 19 N doubles):
+ * post-collision, or pre-collision in the in-place form.  Asynchronous. */
 clbm_status clbm_populations(clbm_lattice *h, double *f_dev, void *stream);
 
-/* FP64 reductions over the lattice (synchronizes `stream`):
+/* FP64 reductions over the fluid nodes (the conserved mass and momentum of
+ * the collision, Sec. 3; the steady-state criterion of the cavity runs,
+ * Sec. 4.3), synchronizes `stream`:
  *   out[0] total mass sum rho          out[4] residual |u - u_prev|_2 / |u|_2
  *   out[1..3] total momentum sum rho u     against the previous clbm_reduce
- *                                          (0 on the first call or if untracked)
+ *                                          (0 on the first call or if untracked;
+ *                                          the previous velocity is kept in FP64)
  *   out[5] number of nodes with non-finite populations
  *   out[6] max |u|                     out[7] kinetic energy sum rho |u|^2 / 2
  * Returns CLBM_EUNSTABLE (after filling out) if out[5] > 0. */
@@ -210,7 +253,7 @@ clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream);
 
 /* Index (0 = pop_a, 1 = pop_b; always 0 in the in-place form) of the buffer
  * holding the current state, and the number of steps taken since the last
- * init. */
+ * init.  Either output may be NULL. */
 clbm_status clbm_state(clbm_lattice *h, int *buffer_index, int64_t *steps_done);
 
 /* Launch configuration of the stream-collide kernel (results do not depend
@@ -257,6 +300,9 @@ clbm_status clbm_get_block(clbm_lattice *h, int32_t *bx, int32_t *by);
  * whose steps overwrite the state, and before an init call (ESTATE). */
 clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, double *best_ms);
 
+/* Release the handle and the library's own memory (never the caller's
+ * buffers or flags).  NULL is accepted.  Work already queued on a stream must
+ * not be outstanding. */
 clbm_status clbm_destroy(clbm_lattice *h);
 
 /* Message for the last failing call on this thread ("" if none). */
@@ -289,26 +335,35 @@ typedef struct {
 /* Bytes each of the two pools must hold for these instances. */
 clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *bytes_each);
 
-/* Create a batch over two caller-owned pools.  Validates every instance
- * (EINVAL, with the instance index in the message); allocates the instance
- * descriptors, the tile table and reduction scratch; reads the tuned launch
- * configuration from tune_cache_path (nullable) when it holds an entry for
- * exactly this set of instances. */
+/* Create a batch of independent instances, each a problem statement as for
+ * clbm_create (Sec. 4: dimensions, K and n of Eq. 5, lid or force), over two
+ * caller-owned pools of bytes_each >= clbm_batch_size bytes (256-byte
+ * aligned device memory).  Validates every instance (EINVAL, with the
+ * instance index in the message); allocates the instance descriptors, the
+ * tile table and reduction scratch; reads the tuned launch configuration
+ * from tune_cache_path (nullable) when it holds an entry for exactly this set
+ * of instances. */
 clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool_a, void *pool_b,
                               size_t bytes_each, const char *tune_cache_path, clbm_batch **out);
 
+/* Rest state for every instance, or caller populations for instance i, as
+ * clbm_init_rest and clbm_init_populations (on_device as there). */
 clbm_status clbm_batch_init_rest(clbm_batch *b, void *stream);
-clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0_dev, void *stream);
+clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0, int on_device, void *stream);
 
-/* Advance every instance by nsteps: one launch per step over all tiles,
- * replayed from captured graphs in chunks of graph_steps. */
+/* Advance every instance by nsteps (the time step of clbm_step, Sec. 3):
+ * one persistent launch per step over all tiles, replayed from captured
+ * graphs in chunks of graph_steps.  Asynchronous; the first call for a
+ * graph length and buffer parity instantiates its graph. */
 clbm_status clbm_batch_step(clbm_batch *b, int64_t nsteps, void *stream);
 
 /* Reference path with the same results: one single-lattice launch per
  * instance per step. */
 clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream);
 
-clbm_status clbm_batch_macroscopic(clbm_batch *b, int32_t i, double *rho_dev, double *u_dev, void *stream);
+/* Outputs of instance i, as clbm_macroscopic and clbm_populations. */
+clbm_status clbm_batch_macroscopic(clbm_batch *b, int32_t i, void *rho_dev, void *u_dev, int32_t out_prec,
+                                   void *stream);
 clbm_status clbm_batch_populations(clbm_batch *b, int32_t i, double *f_dev, void *stream);
 
 /* FP64 reductions of clbm_reduce for every instance: out[8*i + k]

@@ -55,6 +55,8 @@ class _Params(ctypes.Structure):
         ("lid_velocity", ctypes.c_double * 3),
         ("rho_wall", ctypes.c_double),
         ("model", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("flags", ctypes.c_void_p),
     ]
 
 
@@ -83,7 +85,23 @@ def _load():
     return lib
 
 
-def _params(spec) -> _Params:
+#: per-node solid flags (uint8, shape (nz, ny, nx)): fluid, wall, moving wall
+FLUID, WALL, MOVING_WALL = 0, 1, 2
+
+
+def _flags(spec, flags):
+    """C-contiguous uint8 copy of a flag array (or None)."""
+    if flags is None:
+        return None
+    a = np.ascontiguousarray(flags, dtype=np.uint8).reshape(_shape(spec)[1:])
+    if a.max(initial=0) > MOVING_WALL:
+        raise ValueError("flags must be 0 (fluid), 1 (wall) or 2 (moving wall)")
+    return a
+
+
+def _params(spec, flags=None) -> _Params:
+    """C parameters; `flags` (a uint8 array from _flags, kept alive by the
+    caller during the call) marks solid nodes."""
     p = _Params()
     p.nx, p.ny, p.nz = int(spec.nx), int(spec.ny), int(spec.nz)
     for d in range(3):
@@ -102,6 +120,7 @@ def _params(spec) -> _Params:
     if model not in ("cascaded", "srt"):
         raise ValueError(f"unknown model {model!r}")
     p.model = 1 if model == "srt" else 0
+    p.flags = flags.ctypes.data if flags is not None else None
     return p
 
 
@@ -158,40 +177,47 @@ def collide_node(spec, f: np.ndarray):
     return out, float(om[0])
 
 
-def collide(spec, f: np.ndarray, with_omega: bool = False):
-    """Post-collision populations of every node (and omega^nu if asked)."""
+def collide(spec, f: np.ndarray, with_omega: bool = False, flags=None):
+    """Post-collision populations of every node (and omega^nu if asked);
+    nodes flagged solid hold the rest populations."""
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(_shape(spec))
     out = np.empty_like(f)
     om = np.empty(_shape(spec)[1:]) if with_omega else None
-    p = _params(spec)
+    fl = _flags(spec, flags)
+    p = _params(spec, fl)
     _check(_load().orc_collide(ctypes.byref(p), _ptr(f), _ptr(out),
                                _ptr(om) if om is not None else None), "collide")
     return (out, om) if with_omega else out
 
 
-def stream(spec, ft: np.ndarray) -> np.ndarray:
-    """Pull streaming of post-collision populations with the boundary rules."""
+def stream(spec, ft: np.ndarray, flags=None) -> np.ndarray:
+    """Pull streaming of post-collision populations with the boundary rules
+    (solid nodes of `flags` bounce back like the walls of the box)."""
     ft = np.ascontiguousarray(ft, dtype=np.float64).reshape(_shape(spec))
     out = np.empty_like(ft)
-    p = _params(spec)
+    fl = _flags(spec, flags)
+    p = _params(spec, fl)
     _check(_load().orc_stream(ctypes.byref(p), _ptr(ft), _ptr(out)), "stream")
     return out
 
 
-def run(spec, f0: np.ndarray, steps: int) -> np.ndarray:
+def run(spec, f0: np.ndarray, steps: int, flags=None) -> np.ndarray:
     """Pre-collision state after `steps` collide+stream steps from f0."""
     f = np.array(f0, dtype=np.float64, copy=True).reshape(_shape(spec))
     f = np.ascontiguousarray(f)
-    p = _params(spec)
+    fl = _flags(spec, flags)
+    p = _params(spec, fl)
     _check(_load().orc_run(ctypes.byref(p), _ptr(f), int(steps)), "run")
     return f
 
 
-def macroscopic(spec, f: np.ndarray):
-    """(rho, u) of a pre-collision state; u has shape (3, nz, ny, nx)."""
+def macroscopic(spec, f: np.ndarray, flags=None):
+    """(rho, u) of a pre-collision state; u has shape (3, nz, ny, nx); solid
+    nodes report rho = 1, u = 0."""
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(_shape(spec))
     rho = np.empty(_shape(spec)[1:])
     u = np.empty((3,) + _shape(spec)[1:])
-    p = _params(spec)
+    fl = _flags(spec, flags)
+    p = _params(spec, fl)
     _check(_load().orc_macroscopic(ctypes.byref(p), _ptr(f), _ptr(rho), _ptr(u)), "macroscopic")
     return rho, u

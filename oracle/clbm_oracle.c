@@ -72,7 +72,14 @@ typedef struct {
     double lid_velocity[3];
     double rho_wall;       /* density in the moving-wall correction */
     int32_t model;         /* 0: the cascaded scheme; 1: single-relaxation-time BGK (comparison model) */
+    int32_t pad_;
+    const uint8_t *flags;  /* per-node solid flags (NULL: every node is fluid): 0 fluid, 1 wall,
+                              2 wall moving with lid_velocity */
 } orc_params;
+
+enum { FLAG_FLUID = 0, FLAG_WALL = 1, FLAG_MOVING_WALL = 2 };
+
+static int is_solid(const orc_params *p, int64_t i) { return p->flags && p->flags[i] != FLAG_FLUID; }
 
 /* D3Q19 particle velocities, alpha = 0..18, read off the component vectors
  * |e_x>, |e_y>, |e_z> given with the moment basis in Sec. 3. */
@@ -481,7 +488,9 @@ int orc_set_threads(int t) {
 #endif
 }
 
-/* Collide every node: fout = C(fin); omega (nullable) receives omega^nu. */
+/* Collide every fluid node: fout = C(fin); omega (nullable) receives
+ * omega^nu.  Solid nodes (flags) are not part of the fluid: they hold the
+ * rest populations w and report omega = 0. */
 int orc_collide(const orc_params *p, const double *fin, double *fout, double *omega) {
     if (!valid_params(p)) return -1;
     init_tables();
@@ -490,6 +499,11 @@ int orc_collide(const orc_params *p, const double *fin, double *fout, double *om
 #pragma omp parallel for schedule(static) reduction(| : err)
     for (int64_t i = 0; i < N; ++i) {
         double a_in[Q], a_out[Q], om;
+        if (is_solid(p, i)) {
+            for (int a = 0; a < Q; ++a) fout[a * N + i] = W[a];
+            if (omega) omega[i] = 0.0;
+            continue;
+        }
         for (int a = 0; a < Q; ++a) a_in[a] = fin[a * N + i];
         err |= orc_collide_node(p, a_in, a_out, &om) ? 1 : 0;
         for (int a = 0; a < Q; ++a) fout[a * N + i] = a_out[a];
@@ -515,9 +529,11 @@ static int in_lid_plane(const orc_params *p, int sx, int sy, int sz) {
 
 /* Streaming (Eq. cascaded streaming) in pull form: the population moving
  * along e arriving at x left x - e one step earlier.  If x - e is outside the
- * lattice across a wall, half-way bounce-back returns the population that
- * left x toward the wall, plus the moving-wall momentum term
- * 2 w rho_w (e . U_w) / c_s^2. */
+ * lattice across a wall, or is a node flagged solid, half-way bounce-back
+ * (Sec. 4.1) returns the population that left x toward the wall, plus the
+ * moving-wall momentum term 2 w rho_w (e . U_w) / c_s^2 (Sec. 4.3) when the
+ * wall moves: a ghost in the lid plane, or a node flagged as moving wall.
+ * Solid nodes keep the rest populations. */
 int orc_stream(const orc_params *p, const double *ft, double *f) {
     if (!valid_params(p)) return -1;
     init_tables();
@@ -526,6 +542,10 @@ int orc_stream(const orc_params *p, const double *ft, double *f) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+        if (is_solid(p, i)) {
+            for (int a = 0; a < Q; ++a) f[a * N + i] = W[a];
+            continue;
+        }
         for (int a = 0; a < Q; ++a) {
             int sx = x - EX[a], sy = y - EY[a], sz = z - EZ[a];
             int ghost = 0;
@@ -533,12 +553,20 @@ int orc_stream(const orc_params *p, const double *ft, double *f) {
             if (p->periodic[0]) wx = (sx + nx) % nx; else if (sx < 0 || sx >= nx) ghost = 1;
             if (p->periodic[1]) wy = (sy + ny) % ny; else if (sy < 0 || sy >= ny) ghost = 1;
             if (p->periodic[2]) wz = (sz + nz) % nz; else if (sz < 0 || sz >= nz) ghost = 1;
+            int moving = 0;
             if (!ghost) {
                 int64_t s = (int64_t)wx + (int64_t)nx * ((int64_t)wy + (int64_t)ny * wz);
-                f[a * N + i] = ft[a * N + s];
+                if (!is_solid(p, s)) {
+                    f[a * N + i] = ft[a * N + s];
+                    continue;
+                }
+                moving = p->flags[s] == FLAG_MOVING_WALL;
             } else {
+                moving = in_lid_plane(p, sx, sy, sz);
+            }
+            {
                 double corr = 0.0;
-                if (in_lid_plane(p, sx, sy, sz)) {
+                if (moving) {
                     double eu = EX[a] * p->lid_velocity[0] + EY[a] * p->lid_velocity[1] +
                                 EZ[a] * p->lid_velocity[2];
                     corr = 2.0 * W[a] * p->rho_wall * eu / CS2;
@@ -566,12 +594,18 @@ int orc_run(const orc_params *p, double *f, int64_t steps) {
 }
 
 /* Density and velocity of a pre-collision state: rho = sum f and
- * u = (sum e f + F/2) / rho.  u is stored as three planes (ux, uy, uz). */
+ * u = (sum e f + F/2) / rho.  u is stored as three planes (ux, uy, uz).
+ * Solid nodes report rho = 1, u = 0. */
 int orc_macroscopic(const orc_params *p, const double *f, double *rho, double *u) {
     if (!valid_params(p)) return -1;
     int64_t N = nnodes(p);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
+        if (is_solid(p, i)) {
+            rho[i] = 1.0;
+            u[i] = u[N + i] = u[2 * N + i] = 0.0;
+            continue;
+        }
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
         for (int a = 0; a < Q; ++a) {
             double v = f[a * N + i];

@@ -1,6 +1,12 @@
-"""Compile the HIP library libclbm.so for gfx950 (in-tree)."""
+"""Compile the HIP library libclbm.so for gfx950 (in-tree).
+
+The library carries a hash of the sources it was built from (returned by
+clbm_version()); the binding compares it with the sources in the tree and
+refuses a stale library.
+"""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -19,6 +25,21 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Wno-unused-command-line-argument"]
 
 
+def source_hash() -> str:
+    """Hash of every source the library is built from (kernels, runtime,
+    the public header) and of the compiler flags."""
+    h = hashlib.sha256()
+    files = sorted(os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc"))
+                   if f.endswith((".hip", ".hpp", ".h")))
+    files.append(os.path.join(ROOT, "include", "clbm.h"))
+    for path in files:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     return os.path.join(rocm, "bin", "hipcc")
@@ -28,7 +49,8 @@ def build(verbose: bool = False) -> str:
     """Compile each source to an object (in parallel), then link the library."""
     tag = ".tmp%d" % os.getpid()
     objs = [os.path.join(HERE, "csrc", os.path.basename(src) + tag + ".o") for src in SOURCES]
-    cmds = [[hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+    defs = ['-DCLBM_SOURCE_HASH="%s"' % source_hash()]
+    cmds = [[hipcc()] + HIPCC_FLAGS + defs + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
             for src, obj in zip(SOURCES, objs)]
     try:
         with ThreadPoolExecutor(max_workers=len(cmds)) as ex:

@@ -21,6 +21,9 @@ LAYOUT = {"planes": 0, "rows": 1}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
 
 CLBM_OK, CLBM_EINVAL, CLBM_ENOMEM, CLBM_EHIP, CLBM_EUNSTABLE, CLBM_ESTATE = 0, -1, -2, -3, -4, -5
+CLBM_FLUID, CLBM_WALL, CLBM_MOVING_WALL = 0, 1, 2
+OUT_PREC = {"f64": 0, "f32": 1}
+OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32}
 
 
 class ClbmError(RuntimeError):
@@ -71,12 +74,12 @@ _PP = ctypes.POINTER(Params)
 SIGNATURES = {
     "clbm_params_default": (ctypes.c_int, [_PP]),
     "clbm_buffer_size": (ctypes.c_int, [_PP, _I64P, ctypes.POINTER(ctypes.c_size_t)]),
-    "clbm_create": (ctypes.c_int, [_PP, _VP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    "clbm_create": (ctypes.c_int, [_PP, _VP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     "clbm_create_in_place": (ctypes.c_int, [_PP, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
     "clbm_init_rest": (ctypes.c_int, [_VP, _VP]),
-    "clbm_init_populations": (ctypes.c_int, [_VP, _VP, _VP]),
+    "clbm_init_populations": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
     "clbm_step": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
-    "clbm_macroscopic": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "clbm_macroscopic": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP]),
     "clbm_populations": (ctypes.c_int, [_VP, _VP, _VP]),
     "clbm_reduce": (ctypes.c_int, [_VP, _DP, _VP]),
     "clbm_state": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int), _I64P]),
@@ -94,10 +97,10 @@ SIGNATURES = {
     "clbm_batch_create": (ctypes.c_int, [_PP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, ctypes.c_char_p,
                                          ctypes.POINTER(_VP)]),
     "clbm_batch_init_rest": (ctypes.c_int, [_VP, _VP]),
-    "clbm_batch_init_populations": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "clbm_batch_init_populations": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, ctypes.c_int, _VP]),
     "clbm_batch_step": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
     "clbm_batch_step_each": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
-    "clbm_batch_macroscopic": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "clbm_batch_macroscopic": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32, _VP]),
     "clbm_batch_populations": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
     "clbm_batch_reduce": (ctypes.c_int, [_VP, _DP, _VP]),
     "clbm_batch_autotune": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(BatchConfig), _DP]),
@@ -109,7 +112,8 @@ SIGNATURES = {
 
 
 def load():
-    """Load libclbm.so (raises if it has not been built)."""
+    """Load libclbm.so.  Raises if it has not been built, or if it was built
+    from other sources than those in the tree (stale library)."""
     global _lib
     if _lib is not None:
         return _lib
@@ -121,6 +125,12 @@ def load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    from . import build as _build
+    built = lib.clbm_version().decode().rsplit(" src ", 1)[-1]
+    want = _build.source_hash()
+    if built != want:
+        raise ImportError(f"{LIBPATH} was built from other sources (hash {built}, tree {want}); rebuild it "
+                          "with __graft_entry__.build()")
     _lib = lib
     return lib
 
@@ -201,9 +211,12 @@ class Lattice:
 
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
                  block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto",
-                 in_place: bool = False, layout: str = None):
+                 in_place: bool = False, layout: str = None, flags: torch.Tensor = None):
         """layout: "rows" or "planes"; None picks planes for two steps per
-        launch (which need them), rows otherwise."""
+        launch (which need them), rows otherwise.  flags: optional uint8
+        tensor of shape (nz, ny, nx) with CLBM_FLUID / CLBM_WALL /
+        CLBM_MOVING_WALL per node (kept on the device for the lattice's
+        lifetime)."""
         lib = load()
         self.spec = spec
         self.storage = storage
@@ -217,14 +230,21 @@ class Lattice:
         self.device = torch.device(device)
         nbuf = 1 if self.in_place else 2
         self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(nbuf)]
+        self.flags = None
+        if flags is not None:
+            if self.in_place:
+                raise ValueError("the one-buffer form takes no per-node flags")
+            self.flags = flags.to(device=self.device, dtype=torch.uint8).contiguous()
+            assert self.flags.numel() == self.nodes, "flags must hold nx*ny*nz values"
         h = ctypes.c_void_p()
         if self.in_place:
             _check(lib.clbm_create_in_place(ctypes.byref(self.params), ctypes.c_void_p(self.buffers[0].data_ptr()),
                                             ctypes.c_size_t(self.nbytes), ctypes.byref(h)))
         else:
+            fl = ctypes.c_void_p(self.flags.data_ptr()) if self.flags is not None else None
             _check(lib.clbm_create(ctypes.byref(self.params), ctypes.c_void_p(self.buffers[0].data_ptr()),
                                    ctypes.c_void_p(self.buffers[1].data_ptr()), ctypes.c_size_t(self.nbytes),
-                                   ctypes.byref(h)))
+                                   fl, ctypes.byref(h)))
         self._h = h
         if block is not None:
             self.set_block(*block)
@@ -255,12 +275,15 @@ class Lattice:
         _check(load().clbm_init_rest(self._h, _stream(stream)))
 
     def init_populations(self, f0: torch.Tensor, stream=None):
-        """f0: float64 device tensor of shape (19, nz, ny, nx)."""
-        f0 = f0.to(device=self.device, dtype=torch.float64).contiguous()
+        """f0: float64 tensor of shape (19, nz, ny, nx) on the device, or on
+        the host (the library then stages it and synchronizes)."""
+        on_device = f0.is_cuda
+        f0 = f0.to(device=self.device if on_device else "cpu", dtype=torch.float64).contiguous()
         assert f0.numel() == Q * self.nodes, "f0 must hold 19 x nx*ny*nz values"
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _check(load().clbm_init_populations(self._h, ctypes.c_void_p(f0.data_ptr()), _stream(s)))
-        if s != torch.cuda.current_stream(self.device):
+        _check(load().clbm_init_populations(self._h, ctypes.c_void_p(f0.data_ptr()), 1 if on_device else 0,
+                                            _stream(s)))
+        if on_device and s != torch.cuda.current_stream(self.device):
             f0.record_stream(s)     # the launch may still read f0 after this returns
 
     def step(self, nsteps: int, stream=None):
@@ -293,11 +316,14 @@ class Lattice:
         return flat[:Q * self.nodes].view(nz, ny, Q, nx).permute(2, 0, 1, 3)
 
     # -- outputs -----------------------------------------------------------
-    def macroscopic(self, stream=None):
-        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+    def macroscopic(self, stream=None, out_prec: str = "f64"):
+        """(rho, u) at the current time, u of shape (3, nz, ny, nx), as float64
+        (out_prec "f64") or float32 ("f32")."""
+        dt = OUT_DTYPE[out_prec]
+        rho = torch.empty(self.shape, dtype=dt, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=dt, device=self.device)
         _check(load().clbm_macroscopic(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
-                                       _stream(stream)))
+                                       OUT_PREC[out_prec], _stream(stream)))
         return rho, u
 
     def populations(self, stream=None) -> torch.Tensor:
@@ -393,11 +419,13 @@ class Batch:
 
     def init_populations(self, i: int, f0: torch.Tensor, stream=None):
         sp = self.specs[i]
-        f0 = f0.to(device=self.device, dtype=torch.float64).contiguous()
+        on_device = f0.is_cuda
+        f0 = f0.to(device=self.device if on_device else "cpu", dtype=torch.float64).contiguous()
         assert f0.numel() == Q * sp.nx * sp.ny * sp.nz
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _check(load().clbm_batch_init_populations(self._h, int(i), ctypes.c_void_p(f0.data_ptr()), _stream(s)))
-        if s != torch.cuda.current_stream(self.device):
+        _check(load().clbm_batch_init_populations(self._h, int(i), ctypes.c_void_p(f0.data_ptr()),
+                                                  1 if on_device else 0, _stream(s)))
+        if on_device and s != torch.cuda.current_stream(self.device):
             f0.record_stream(s)
 
     def step(self, nsteps: int, stream=None):
@@ -406,13 +434,14 @@ class Batch:
     def step_each(self, nsteps: int, stream=None):
         _check(load().clbm_batch_step_each(self._h, int(nsteps), _stream(stream)))
 
-    def macroscopic(self, i: int, stream=None):
+    def macroscopic(self, i: int, stream=None, out_prec: str = "f64"):
         sp = self.specs[i]
         shape = (sp.nz, sp.ny, sp.nx)
-        rho = torch.empty(shape, dtype=torch.float64, device=self.device)
-        u = torch.empty((3,) + shape, dtype=torch.float64, device=self.device)
+        dt = OUT_DTYPE[out_prec]
+        rho = torch.empty(shape, dtype=dt, device=self.device)
+        u = torch.empty((3,) + shape, dtype=dt, device=self.device)
         _check(load().clbm_batch_macroscopic(self._h, int(i), ctypes.c_void_p(rho.data_ptr()),
-                                             ctypes.c_void_p(u.data_ptr()), _stream(stream)))
+                                             ctypes.c_void_p(u.data_ptr()), OUT_PREC[out_prec], _stream(stream)))
         return rho, u
 
     def populations(self, i: int, stream=None):

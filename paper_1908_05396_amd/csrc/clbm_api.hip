@@ -19,6 +19,7 @@ struct clbm_lattice {
     bool forced;
     int route;
     bool in_place;          // one buffer, AA access pattern; stores pre-collision populations
+    const uint8_t *flags;   // caller's per-node solid flags (NULL: the box of the parameters)
     void *buf[2];
     size_t bytes_each;
     int cur;
@@ -30,7 +31,7 @@ struct clbm_lattice {
     double *result;
     double *host_result;
     int nblocks;
-    float *snapshot;
+    double *snapshot;       // FP64 velocity of the previous reduction (residual)
     bool have_snapshot;
 };
 
@@ -61,7 +62,10 @@ extern "C" {
 
 const char *clbm_last_error(void) { return g_err.c_str(); }
 
-const char *clbm_version(void) { return "clbm 0.1 (gfx950, D3Q19 cascaded power-law)"; }
+#ifndef CLBM_SOURCE_HASH
+#define CLBM_SOURCE_HASH "unknown"
+#endif
+const char *clbm_version(void) { return "clbm 0.2 (gfx950, D3Q19 cascaded power-law) src " CLBM_SOURCE_HASH; }
 
 clbm_status clbm_lattice_tables(int32_t *e, int32_t *o, double *w) {
     for (int a = 0; a < Q; ++a) {
@@ -108,7 +112,7 @@ clbm_status clbm_buffer_size(const clbm_params *p, int64_t *plane, size_t *bytes
 }
 
 static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, bool in_place,
-                                 clbm_lattice **out) {
+                                 const uint8_t *flags, clbm_lattice **out) {
     if (!out) return fail(CLBM_EINVAL, "out is NULL");
     *out = nullptr;
     clbm_status st = validate(p);
@@ -130,6 +134,7 @@ static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b,
     h->forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
     h->route = route_of(p);
     h->in_place = in_place;
+    h->flags = flags;
     h->buf[0] = pop_a;
     h->buf[1] = pop_b;
     h->bytes_each = bytes_each;
@@ -160,21 +165,35 @@ static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b,
         h->result = h->partials + (size_t)kReduceSlots * h->nblocks;
         e = hipHostMalloc((void **)&h->host_result, sizeof(double) * kReduceSlots, hipHostMallocDefault);
     }
-    if (e == hipSuccess && p->track_residual) e = hipMalloc((void **)&h->snapshot, sizeof(float) * 3 * N);
+    if (e == hipSuccess && p->track_residual) e = hipMalloc((void **)&h->snapshot, sizeof(double) * 3 * N);
     if (e != hipSuccess) {
         clbm_destroy(h);
         return hip_fail(e, "clbm_create: scratch allocation");
+    }
+    if (flags) {
+        // every flag must be fluid, wall or moving wall (checked once, here)
+        e = launch_check_flags(flags, N, h->result, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(h->host_result, h->result, sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            clbm_destroy(h);
+            return hip_fail(e, "clbm_create: flag check");
+        }
+        if (h->host_result[0] != 0.0) {
+            clbm_destroy(h);
+            return fail(CLBM_EINVAL, "flags hold values other than 0 (fluid), 1 (wall) and 2 (moving wall)");
+        }
     }
     *out = h;
     return CLBM_OK;
 }
 
-clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, clbm_lattice **out) {
-    return create_common(p, pop_a, pop_b, bytes_each, false, out);
+clbm_status clbm_create(const clbm_params *p, void *pop_a, void *pop_b, size_t bytes_each, const uint8_t *flags,
+                        clbm_lattice **out) {
+    return create_common(p, pop_a, pop_b, bytes_each, false, flags, out);
 }
 
 clbm_status clbm_create_in_place(const clbm_params *p, void *pop, size_t bytes, clbm_lattice **out) {
-    return create_common(p, pop, pop, bytes, true, out);
+    return create_common(p, pop, pop, bytes, true, nullptr, out);
 }
 
 clbm_status clbm_destroy(clbm_lattice *h) {
@@ -186,17 +205,42 @@ clbm_status clbm_destroy(clbm_lattice *h) {
     return CLBM_OK;
 }
 
-clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, void *stream) {
+// A temporary device copy of host populations (19 N doubles), released by
+// the caller after the stream has consumed it.
+static clbm_status stage_host_populations(const double *f0_host, int64_t N, hipStream_t st, double **dev) {
+    *dev = nullptr;
+    HIP_TRY(hipMalloc((void **)dev, sizeof(double) * Q * (size_t)N), "init: staging allocation");
+    hipError_t e = hipMemcpyAsync(*dev, f0_host, sizeof(double) * Q * (size_t)N, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        return hip_fail(e, "init: copy of the host populations");
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, int on_device, void *stream) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     if (!f0) return fail(CLBM_EINVAL, "f0 is NULL");
+    if (on_device != 0 && on_device != 1) return fail(CLBM_EINVAL, "on_device must be 0 or 1");
+    hipStream_t st = (hipStream_t)stream;
+    const double *src = f0;
+    double *staged = nullptr;
+    if (!on_device) {
+        clbm_status s = stage_host_populations(f0, (int64_t)h->geom.n, st, &staged);
+        if (s != CLBM_OK) return s;
+        src = staged;
+    }
     h->cur = 0;
-    if (h->in_place)
-        HIP_TRY(launch_store_plain(h->prm.storage, f0, h->buf[0], h->geom, (hipStream_t)stream),
-                "clbm_init_populations");
-    else
-        HIP_TRY(launch_init(h->prm.storage, f0, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
-                            (hipStream_t)stream),
-                "clbm_init_populations");
+    hipError_t e = h->in_place ? launch_store_plain(h->prm.storage, src, h->buf[0], h->geom, st)
+                               : launch_init(h->prm.storage, src, h->buf[0], h->flags, h->geom, h->rd, h->rf,
+                                             h->forced, h->route, st);
+    if (staged) {
+        hipError_t e2 = hipStreamSynchronize(st);
+        (void)hipFree(staged);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "clbm_init_populations");
     h->initialized = true;
     h->steps_done = 0;
     h->have_snapshot = false;
@@ -211,8 +255,8 @@ clbm_status clbm_init_rest(clbm_lattice *h, void *stream) {
         HIP_TRY(launch_store_plain(h->prm.storage, nullptr, h->buf[0], h->geom, (hipStream_t)stream),
                 "clbm_init_rest");
     else
-        HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
-                            (hipStream_t)stream),
+        HIP_TRY(launch_init(h->prm.storage, nullptr, h->buf[0], h->flags, h->geom, h->rd, h->rf, h->forced,
+                            h->route, (hipStream_t)stream),
                 "clbm_init_rest");
     h->initialized = true;
     h->steps_done = 0;
@@ -233,6 +277,16 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
                                    h->launch, st),
                     "clbm_step (in place)");
             h->steps_done += 2;
+        }
+        return CLBM_OK;
+    }
+    if (h->flags) {
+        for (int64_t t = 0; t < nsteps; ++t) {
+            HIP_TRY(launch_step_flags(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->flags, h->geom, h->rd,
+                                      h->rf, h->forced, h->route, st),
+                    "clbm_step (flagged lattice)");
+            h->cur = 1 - h->cur;
+            h->steps_done++;
         }
         return CLBM_OK;
     }
@@ -261,13 +315,15 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     return CLBM_OK;
 }
 
-clbm_status clbm_macroscopic(clbm_lattice *h, double *rho, double *u, void *stream) {
+clbm_status clbm_macroscopic(clbm_lattice *h, void *rho, void *u, int32_t out_prec, void *stream) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (out_prec != CLBM_F64 && out_prec != CLBM_F32)
+        return fail(CLBM_EINVAL, "out_prec must be CLBM_F64 or CLBM_F32 (got %d)", out_prec);
     if (!h->initialized) return fail(CLBM_ESTATE, "clbm_macroscopic before an init call");
     if (!rho && !u) return CLBM_OK;
     const double F[3] = {h->prm.force[0], h->prm.force[1], h->prm.force[2]};
-    HIP_TRY(launch_macroscopic(h->prm.storage, h->buf[h->cur], rho, u, h->geom, output_force(h, F).data(),
-                               (hipStream_t)stream),
+    HIP_TRY(launch_macroscopic(h->prm.storage, h->buf[h->cur], h->flags, rho, u, out_prec == CLBM_F32, h->geom,
+                               output_force(h, F).data(), (hipStream_t)stream),
             "clbm_macroscopic");
     return CLBM_OK;
 }
@@ -286,15 +342,14 @@ clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream) {
     if (!h->initialized) return fail(CLBM_ESTATE, "clbm_reduce before an init call");
     hipStream_t st = (hipStream_t)stream;
     const double F[3] = {h->prm.force[0], h->prm.force[1], h->prm.force[2]};
-    HIP_TRY(launch_reduce(h->prm.storage, h->buf[h->cur], h->snapshot, h->have_snapshot ? 1 : 0, h->geom,
-                          output_force(h, F).data(), h->partials, h->nblocks, h->result, st),
+    HIP_TRY(launch_reduce(h->prm.storage, h->buf[h->cur], h->flags, h->snapshot, h->have_snapshot ? 1 : 0,
+                          h->geom, output_force(h, F).data(), h->partials, h->nblocks, h->result, st),
             "clbm_reduce");
     HIP_TRY(hipMemcpyAsync(h->host_result, h->result, sizeof(double) * kReduceSlots, hipMemcpyDeviceToHost, st),
             "clbm_reduce: copy");
     HIP_TRY(hipStreamSynchronize(st), "clbm_reduce: sync");
     const double *r = h->host_result;
-    const int64_t N = (int64_t)h->prm.nx * h->prm.ny * h->prm.nz;
-    out[0] = (double)N + r[0];
+    out[0] = r[9] + r[0];      // fluid nodes + sum of (rho - 1)
     out[1] = r[1]; out[2] = r[2]; out[3] = r[3];
     out[4] = (h->snapshot && h->have_snapshot && r[5] > 0.0) ? sqrt(r[4] / r[5]) : 0.0;
     out[5] = r[6];
@@ -326,6 +381,7 @@ clbm_status clbm_set_launch(clbm_lattice *h, const clbm_launch *c) {
     if (c->fuse_steps == 2 && h->in_place) return fail(CLBM_EINVAL, "in-place lattices run one step per launch");
     if (c->fuse_steps == 2 && h->route == 2)
         return fail(CLBM_EINVAL, "the single-relaxation-time model runs one step per launch");
+    if (c->fuse_steps == 2 && h->flags) return fail(CLBM_EINVAL, "flagged lattices run one step per launch");
     if (c->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
     h->launch.bx = c->bx;
     h->launch.by = c->by;
@@ -364,6 +420,7 @@ clbm_status clbm_set_block(clbm_lattice *h, int32_t bx, int32_t by) {
 clbm_status clbm_autotune(clbm_lattice *h, void *stream, clbm_launch *best, double *best_ms) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     if (h->in_place) return fail(CLBM_EINVAL, "autotune: the one-buffer form overwrites its state");
+    if (h->flags) return fail(CLBM_EINVAL, "autotune: flagged lattices run one generic kernel");
     if (!h->initialized) return fail(CLBM_ESTATE, "autotune needs an initialised state");
     hipStream_t st = (hipStream_t)stream;
     const int maxt = h->prm.storage == CLBM_F64 ? 256 : 512;

@@ -169,7 +169,7 @@ struct clbm_batch {
     int nblocks_max;
     double *results;
     double *host_results;
-    std::vector<float *> snapshot;
+    std::vector<double *> snapshot;
     std::vector<char> have_snapshot;
     // graphs
     hipStream_t cap_stream;
@@ -430,7 +430,7 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
     b->snapshot.assign(count, nullptr);
     b->have_snapshot.assign(count, 0);
     for (int i = 0; i < count && e == hipSuccess; ++i)
-        if (inst[i].track_residual) e = hipMalloc((void **)&b->snapshot[i], sizeof(float) * 3 * b->geom[i].n);
+        if (inst[i].track_residual) e = hipMalloc((void **)&b->snapshot[i], sizeof(double) * 3 * b->geom[i].n);
     if (e != hipSuccess) {
         clbm_batch_destroy(b);
         return hip_fail(e, "clbm_batch_create: allocation");
@@ -453,7 +453,7 @@ clbm_status clbm_batch_destroy(clbm_batch *b) {
     if (b->partials) (void)hipFree(b->partials);
     if (b->results) (void)hipFree(b->results);
     if (b->host_results) (void)hipHostFree(b->host_results);
-    for (float *s : b->snapshot)
+    for (double *s : b->snapshot)
         if (s) (void)hipFree(s);
     delete b;
     return CLBM_OK;
@@ -462,7 +462,8 @@ clbm_status clbm_batch_destroy(clbm_batch *b) {
 clbm_status clbm_batch_init_rest(clbm_batch *b, void *stream) {
     if (!b) return fail(CLBM_EINVAL, "batch handle is NULL");
     for (int i = 0; i < b->count; ++i)
-        HIP_TRY(launch_init(b->storage, nullptr, (void *)storage_ptr(b, 0, i), b->geom[i], b->rd[i], b->rf[i],
+        HIP_TRY(launch_init(b->storage, nullptr, (void *)storage_ptr(b, 0, i), nullptr, b->geom[i], b->rd[i],
+                            b->rf[i],
                             b->forced[i], b->route, (hipStream_t)stream),
                 "clbm_batch_init_rest");
     b->cur = 0;
@@ -472,14 +473,33 @@ clbm_status clbm_batch_init_rest(clbm_batch *b, void *stream) {
     return CLBM_OK;
 }
 
-clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0, void *stream) {
+clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0, int on_device, void *stream) {
     clbm_status st = check_index(b, i);
     if (st != CLBM_OK) return st;
     if (!f0) return fail(CLBM_EINVAL, "f0 is NULL");
+    if (on_device != 0 && on_device != 1) return fail(CLBM_EINVAL, "on_device must be 0 or 1");
     if (!b->initialized) return fail(CLBM_ESTATE, "initialise the batch with clbm_batch_init_rest first");
-    HIP_TRY(launch_init(b->storage, f0, (void *)storage_ptr(b, b->cur, i), b->geom[i], b->rd[i], b->rf[i],
-                        b->forced[i], b->route, (hipStream_t)stream),
-            "clbm_batch_init_populations");
+    hipStream_t s = (hipStream_t)stream;
+    const double *src = f0;
+    double *staged = nullptr;
+    if (!on_device) {
+        const size_t bytes = sizeof(double) * Q * (size_t)b->geom[i].n;
+        HIP_TRY(hipMalloc((void **)&staged, bytes), "clbm_batch_init_populations: staging allocation");
+        hipError_t e = hipMemcpyAsync(staged, f0, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            (void)hipFree(staged);
+            return hip_fail(e, "clbm_batch_init_populations: copy");
+        }
+        src = staged;
+    }
+    hipError_t e = launch_init(b->storage, src, (void *)storage_ptr(b, b->cur, i), nullptr, b->geom[i], b->rd[i],
+                               b->rf[i], b->forced[i], b->route, s);
+    if (staged) {
+        hipError_t e2 = hipStreamSynchronize(s);
+        (void)hipFree(staged);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "clbm_batch_init_populations");
     b->have_snapshot[i] = 0;
     return CLBM_OK;
 }
@@ -544,13 +564,15 @@ clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream) {
     return CLBM_OK;
 }
 
-clbm_status clbm_batch_macroscopic(clbm_batch *b, int32_t i, double *rho, double *u, void *stream) {
+clbm_status clbm_batch_macroscopic(clbm_batch *b, int32_t i, void *rho, void *u, int32_t out_prec, void *stream) {
     clbm_status st = check_index(b, i);
     if (st != CLBM_OK) return st;
+    if (out_prec != CLBM_F64 && out_prec != CLBM_F32)
+        return fail(CLBM_EINVAL, "out_prec must be CLBM_F64 or CLBM_F32 (got %d)", out_prec);
     if (!b->initialized) return fail(CLBM_ESTATE, "clbm_batch_macroscopic before an init call");
     if (!rho && !u) return CLBM_OK;
-    HIP_TRY(launch_macroscopic(b->storage, storage_ptr(b, b->cur, i), rho, u, b->geom[i], b->prm[i].force,
-                               (hipStream_t)stream),
+    HIP_TRY(launch_macroscopic(b->storage, storage_ptr(b, b->cur, i), nullptr, rho, u, out_prec == CLBM_F32,
+                               b->geom[i], b->prm[i].force, (hipStream_t)stream),
             "clbm_batch_macroscopic");
     return CLBM_OK;
 }
@@ -573,7 +595,8 @@ clbm_status clbm_batch_reduce(clbm_batch *b, double *out, void *stream) {
     for (int i = 0; i < b->count; ++i) {
         const int nb = (int)std::min<int64_t>(b->nblocks_max, ((int64_t)b->geom[i].n + kReduceThreads - 1) /
                                                                    kReduceThreads);
-        HIP_TRY(launch_reduce(b->storage, storage_ptr(b, b->cur, i), b->snapshot[i], b->have_snapshot[i] ? 1 : 0,
+        HIP_TRY(launch_reduce(b->storage, storage_ptr(b, b->cur, i), nullptr, b->snapshot[i],
+                              b->have_snapshot[i] ? 1 : 0,
                               b->geom[i], b->prm[i].force, b->partials, nb, b->results + (size_t)kReduceSlots * i,
                               st),
                 "clbm_batch_reduce");
@@ -586,7 +609,7 @@ clbm_status clbm_batch_reduce(clbm_batch *b, double *out, void *stream) {
     for (int i = 0; i < b->count; ++i) {
         const double *r = b->host_results + (size_t)kReduceSlots * i;
         double *o = out + 8 * (size_t)i;
-        o[0] = (double)b->geom[i].n + r[0];
+        o[0] = r[9] + r[0];
         o[1] = r[1]; o[2] = r[2]; o[3] = r[3];
         o[4] = (b->snapshot[i] && b->have_snapshot[i] && r[5] > 0.0) ? sqrt(r[4] / r[5]) : 0.0;
         o[5] = r[6];

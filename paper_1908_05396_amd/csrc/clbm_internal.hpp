@@ -30,7 +30,7 @@ struct StepLaunch {
     int32_t fuse_rows;      // rows per two-step workgroup, halo rows included (8 or 16)
     int32_t fuse_planes;    // output z planes per two-step workgroup
 };
-constexpr int kReduceSlots = 9;
+constexpr int kReduceSlots = 10;
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                        const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
@@ -41,8 +41,11 @@ hipError_t launch_step2(int storage, const void *A, void *B, const Geom &g, cons
 hipError_t launch_aa_pair(int storage, void *A, const Geom &g, const Relax<double> &pd, const Relax<float> &pf,
                           bool forced, int route, const StepLaunch &c, hipStream_t st);
 hipError_t launch_store_plain(int storage, const double *f0, void *A, const Geom &g, hipStream_t st);
-hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, int route, hipStream_t st);
+hipError_t launch_init(int storage, const double *f0, void *B, const uint8_t *flags, const Geom &g,
+                       const Relax<double> &pd, const Relax<float> &pf, bool forced, int route, hipStream_t st);
+hipError_t launch_step_flags(int storage, const void *A, void *B, const uint8_t *flags, const Geom &g,
+                             const Relax<double> &pd, const Relax<float> &pf, bool forced, int route, hipStream_t st);
+hipError_t launch_check_flags(const uint8_t *flags, int64_t n, double *bad, hipStream_t st);
 
 // Collision forms: 0 = central-moment form for omega_9..18 = 1, 1 = the
 // paper's printed changes of moments g4..g18 with f~ = f + K.g.
@@ -65,11 +68,11 @@ __device__ inline void collide(T d[Q], const Relax<T> &p, T *omega_out) {
 // resolution is 2^-11, takes three (error <= 1.4e-6 on the same envelope).
 template <typename S> struct NewtonSteps { static constexpr int value = 4; };
 template <> struct NewtonSteps<__half> { static constexpr int value = 3; };
-hipError_t launch_macroscopic(int storage, const void *A, double *rho, double *u, const Geom &g,
-                              const double *F, hipStream_t st);
+hipError_t launch_macroscopic(int storage, const void *A, const uint8_t *flags, void *rho, void *u, bool out_f32,
+                              const Geom &g, const double *F, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_export(int storage, const void *A, double *f, const Geom &g, hipStream_t st);
-hipError_t launch_reduce(int storage, const void *A, float *snap, int have_prev, const Geom &g,
-                         const double *F, double *partials, int nblocks, double *out, hipStream_t st);
+hipError_t launch_reduce(int storage, const void *A, const uint8_t *flags, double *snap, int have_prev,
+                         const Geom &g, const double *F, double *partials, int nblocks, double *out, hipStream_t st);
 
 }  // namespace clbm

@@ -1,12 +1,15 @@
 // Kernels of the D3Q19 cascaded power-law LBM for gfx950 and their launchers.
 //
-//   stream_collide  one time step in the planes layout: pull gather + collision
-//                   + store (Sec. 3); the row layout's step is in clbm_rows.hip
-//   init_collide    collide a caller-supplied FP64 state once (time 0), either layout
-//   macroscopic     rho and u from the stored post-collision state
-//   export          f = w + stored deviation, as FP64
-//   reduce          FP64 block partials of mass, momentum, residual, NaNs
-//   reduce_final    fixed-order sum of the partials
+//   stream_collide        one time step in the planes layout: pull gather +
+//                         collision + store (Sec. 3); the row layout's step is in
+//                         clbm_rows.hip
+//   stream_collide_flags  one time step of a lattice with per-node solid flags
+//                         (either layout, one thread per node)
+//   init_collide          collide a caller-supplied FP64 state once (time 0), either layout
+//   macroscopic           rho and u from the stored post-collision state
+//   export                f = w + stored deviation, as FP64
+//   reduce                FP64 block partials of mass, momentum, residual, NaNs
+//   reduce_final          fixed-order sum of the partials
 #include "clbm_internal.hpp"
 
 namespace clbm {
@@ -52,15 +55,81 @@ stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<
 }
 
 // ---------------------------------------------------------------------------
+// Lattices with per-node solid flags (0 fluid, 1 wall, 2 wall moving with the
+// lid velocity).  A fluid node pulls along e_a from x - e_a; when that source
+// is a solid node, or a ghost beyond a wall of the box, half-way bounce-back
+// (Sec. 4.1) returns the node's own post-collision population opposite to a,
+// plus the moving-wall term (Sec. 4.3) for a moving solid node or a ghost in
+// the lid plane.  Solid nodes are not part of the fluid and hold the rest
+// state (zero deviations).  One thread per node in either layout; plain
+// loads (the flags of the 18 neighbours come from cache).
+// ---------------------------------------------------------------------------
+template <typename S, typename T>
+__device__ inline T pull_flagged(const S *__restrict__ A, const uint8_t *__restrict__ flags, const Geom &g,
+                                 const Relax<T> &p, int a, int x, int y, int z) {
+    int sx = x - cx(a), sy = y - cy(a), sz = z - cz(a);
+    bool in_lid = ghost_in_lid(g, sx, sy, sz);
+    bool wall = false;
+    if (sx < 0 || sx >= g.nx) { if (g.px) sx = sx < 0 ? sx + g.nx : sx - g.nx; else wall = true; }
+    if (sy < 0 || sy >= g.ny) { if (g.py) sy = sy < 0 ? sy + g.ny : sy - g.ny; else wall = true; }
+    if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
+    if (!wall) {
+        const uint8_t fs = flags[(int64_t)sx + (int64_t)g.nx * ((int64_t)sy + (int64_t)g.ny * sz)];
+        if (fs == 0) return (T)Conv<S, T>::load(A[elem(g, a, sx, sy, sz)]);
+        in_lid = fs == 2;
+    }
+    return wall_value<T>((T)Conv<S, T>::load(A[elem(g, opp(a), x, y, z)]), p, a, in_lid);
+}
+
+template <typename S, typename T, bool Forced, int Route>
+__global__ void __launch_bounds__(256)
+stream_collide_flags_kernel(const S *__restrict__ A, S *__restrict__ B, const uint8_t *__restrict__ flags, Geom g,
+                            Relax<T> p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)g.n) return;
+    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / g.nxy);
+    T d[Q];
+    if (flags[i] != 0) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) d[a] = T(0);
+    } else {
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            d[a] = a == 0 ? (T)Conv<S, T>::load(A[elem(g, 0, x, y, z)]) : pull_flagged<S, T>(A, flags, g, p, a, x, y, z);
+        collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) B[elem(g, a, x, y, z)] = Conv<S, T>::store(d[a]);
+}
+
+// Any flag other than fluid (0), wall (1) or moving wall (2) sets *bad.
+__global__ void __launch_bounds__(256)
+check_flags_kernel(const uint8_t *__restrict__ flags, int64_t n, double *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flags[i] > 2) *bad = 1.0;
+}
+
+__global__ void __launch_bounds__(64) fill_kernel(double *__restrict__ out, int n, double v) {
+    if ((int)threadIdx.x < n) out[threadIdx.x] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Collide-only initialisation from FP64 populations (unpadded planes); a
-// NULL source means the rest state f = w.
+// NULL source means the rest state f = w.  Solid nodes (flags) hold the rest
+// state.
 // ---------------------------------------------------------------------------
 template <typename S, typename T, bool Forced, int Route>
 __global__ void __launch_bounds__(256)
-init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, Geom g, Relax<T> p) {
+init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, const uint8_t *__restrict__ flags, Geom g,
+                    Relax<T> p) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    if (flags && flags[i] != 0) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) B[elem_i(g, a, i)] = Conv<S, T>::store(T(0));
+        return;
+    }
     T d[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
@@ -88,22 +157,30 @@ __device__ inline void node_moments(const S *__restrict__ A, const Geom &g, int6
     }
 }
 
-template <typename S>
+// Density and velocity in FP64, written as O (double or float); solid nodes
+// report rho = 1, u = 0.
+template <typename S, typename O>
 __global__ void __launch_bounds__(256)
-macroscopic_kernel(const S *__restrict__ A, double *__restrict__ rho, double *__restrict__ u,
-                   Geom g, double fx, double fy, double fz) {
+macroscopic_kernel(const S *__restrict__ A, const uint8_t *__restrict__ flags, O *__restrict__ rho,
+                   O *__restrict__ u, Geom g, double fx, double fy, double fz) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    double D, jx, jy, jz;
-    bool finite;
-    node_moments(A, g, i, D, jx, jy, jz, finite);
-    const double r = 1.0 + D;
-    if (rho) rho[i] = r;
+    double r = 1.0, ux = 0.0, uy = 0.0, uz = 0.0;
+    if (!(flags && flags[i] != 0)) {
+        double D, jx, jy, jz;
+        bool finite;
+        node_moments(A, g, i, D, jx, jy, jz, finite);
+        r = 1.0 + D;
+        ux = (jx - 0.5 * fx) / r;
+        uy = (jy - 0.5 * fy) / r;
+        uz = (jz - 0.5 * fz) / r;
+    }
+    if (rho) rho[i] = (O)r;
     if (u) {
-        u[i] = (jx - 0.5 * fx) / r;
-        u[N + i] = (jy - 0.5 * fy) / r;
-        u[2 * N + i] = (jz - 0.5 * fz) / r;
+        u[i] = (O)ux;
+        u[N + i] = (O)uy;
+        u[2 * N + i] = (O)uz;
     }
 }
 
@@ -122,7 +199,8 @@ export_kernel(const S *__restrict__ A, double *__restrict__ f, Geom g) {
 // ---------------------------------------------------------------------------
 // FP64 reductions: per-block partials, then a single-block fixed-order sum.
 // Slots: 0 sum(rho - 1), 1..3 momentum, 4 sum |u - u_prev|^2, 5 sum |u|^2,
-// 6 non-finite nodes, 7 max |u|, 8 kinetic energy.
+// 6 non-finite nodes, 7 max |u|, 8 kinetic energy, 9 fluid nodes.  Solid
+// nodes (flags) are left out.
 // ---------------------------------------------------------------------------
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -135,14 +213,15 @@ __device__ inline double wave_max(double v) {
 
 template <typename S>
 __global__ void __launch_bounds__(kReduceThreads)
-reduce_kernel(const S *__restrict__ A, float *__restrict__ snap, int have_prev, Geom g, double fx,
-              double fy, double fz, double *__restrict__ partials) {
+reduce_kernel(const S *__restrict__ A, const uint8_t *__restrict__ flags, double *__restrict__ snap, int have_prev,
+              Geom g, double fx, double fy, double fz, double *__restrict__ partials) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     double acc[kReduceSlots];
 #pragma unroll
     for (int k = 0; k < kReduceSlots; ++k) acc[k] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
+        if (flags && flags[i] != 0) continue;
         double D, jx, jy, jz;
         bool finite;
         node_moments(A, g, i, D, jx, jy, jz, finite);
@@ -156,18 +235,18 @@ reduce_kernel(const S *__restrict__ A, float *__restrict__ snap, int have_prev, 
         acc[3] += mz;
         if (snap) {
             if (have_prev) {
-                const double dx = ux - (double)snap[i], dy = uy - (double)snap[N + i],
-                             dz = uz - (double)snap[2 * N + i];
+                const double dx = ux - snap[i], dy = uy - snap[N + i], dz = uz - snap[2 * N + i];
                 acc[4] += dx * dx + dy * dy + dz * dz;
             }
-            snap[i] = (float)ux;
-            snap[N + i] = (float)uy;
-            snap[2 * N + i] = (float)uz;
+            snap[i] = ux;
+            snap[N + i] = uy;
+            snap[2 * N + i] = uz;
         }
         acc[5] += u2;
         acc[6] += finite ? 0.0 : 1.0;
         acc[7] = fmax(acc[7], finite ? sqrt(u2) : 0.0);
         acc[8] += 0.5 * r * u2;
+        acc[9] += 1.0;
     }
     __shared__ double sm[kReduceSlots][kReduceThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -286,53 +365,102 @@ hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const
     }
 }
 
-template <typename S, typename T>
-static hipError_t launch_init_t(const double *f0, void *B, const Geom &g, const Relax<T> &p, bool forced, int route,
-                                hipStream_t st) {
+template <typename S, typename T, bool Forced, int Route>
+static void launch_init_k(const double *f0, void *B, const uint8_t *flags, const Geom &g, const Relax<T> &p,
+                          hipStream_t st) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    hipLaunchKernelGGL((init_collide_kernel<S, T, Forced, Route>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                       st, f0, (S *)B, flags, g, p);
+}
+
+template <typename S, typename T>
+static hipError_t launch_init_t(const double *f0, void *B, const uint8_t *flags, const Geom &g, const Relax<T> &p,
+                                bool forced, int route, hipStream_t st) {
     if (route == 2) {
         if (forced) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((init_collide_kernel<S, T, false, 2>), grid, block, 0, st, f0, (S *)B, g, p);
+        launch_init_k<S, T, false, 2>(f0, B, flags, g, p, st);
     } else if (route == 0) {
-        if (forced)
-            hipLaunchKernelGGL((init_collide_kernel<S, T, true, 0>), grid, block, 0, st, f0, (S *)B, g, p);
-        else
-            hipLaunchKernelGGL((init_collide_kernel<S, T, false, 0>), grid, block, 0, st, f0, (S *)B, g, p);
+        if (forced) launch_init_k<S, T, true, 0>(f0, B, flags, g, p, st);
+        else launch_init_k<S, T, false, 0>(f0, B, flags, g, p, st);
     } else {
-        if (forced)
-            hipLaunchKernelGGL((init_collide_kernel<S, T, true, 1>), grid, block, 0, st, f0, (S *)B, g, p);
-        else
-            hipLaunchKernelGGL((init_collide_kernel<S, T, false, 1>), grid, block, 0, st, f0, (S *)B, g, p);
+        if (forced) launch_init_k<S, T, true, 1>(f0, B, flags, g, p, st);
+        else launch_init_k<S, T, false, 1>(f0, B, flags, g, p, st);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, const double *f0, void *B, const Geom &g, const Relax<double> &pd,
-                       const Relax<float> &pf, bool forced, int route, hipStream_t st) {
+hipError_t launch_init(int storage, const double *f0, void *B, const uint8_t *flags, const Geom &g,
+                       const Relax<double> &pd, const Relax<float> &pf, bool forced, int route, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_init_t<double, double>(f0, B, g, pd, forced, route, st);
-    case 1: return launch_init_t<float, float>(f0, B, g, pf, forced, route, st);
-    default: return launch_init_t<__half, float>(f0, B, g, pf, forced, route, st);
+    case 0: return launch_init_t<double, double>(f0, B, flags, g, pd, forced, route, st);
+    case 1: return launch_init_t<float, float>(f0, B, flags, g, pf, forced, route, st);
+    default: return launch_init_t<__half, float>(f0, B, flags, g, pf, forced, route, st);
     }
 }
 
-template <typename S>
-static hipError_t launch_macro_t(const void *A, double *rho, double *u, const Geom &g, const double *F,
-                                 hipStream_t st) {
+template <typename S, typename T, bool Forced, int Route>
+static void launch_flags_k(const void *A, void *B, const uint8_t *flags, const Geom &g, const Relax<T> &p,
+                           hipStream_t st) {
+    hipLaunchKernelGGL((stream_collide_flags_kernel<S, T, Forced, Route>), dim3((unsigned)((g.n + 255) / 256)),
+                       dim3(256), 0, st, (const S *)A, (S *)B, flags, g, p);
+}
+
+template <typename S, typename T>
+static hipError_t launch_flags_t(const void *A, void *B, const uint8_t *flags, const Geom &g, const Relax<T> &p,
+                                 bool forced, int route, hipStream_t st) {
+    if (route == 2) {
+        if (forced) return hipErrorInvalidValue;
+        launch_flags_k<S, T, false, 2>(A, B, flags, g, p, st);
+    } else if (route == 0) {
+        if (forced) launch_flags_k<S, T, true, 0>(A, B, flags, g, p, st);
+        else launch_flags_k<S, T, false, 0>(A, B, flags, g, p, st);
+    } else {
+        if (forced) launch_flags_k<S, T, true, 1>(A, B, flags, g, p, st);
+        else launch_flags_k<S, T, false, 1>(A, B, flags, g, p, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_flags(int storage, const void *A, void *B, const uint8_t *flags, const Geom &g,
+                             const Relax<double> &pd, const Relax<float> &pf, bool forced, int route, hipStream_t st) {
+    switch (storage) {
+    case 0: return launch_flags_t<double, double>(A, B, flags, g, pd, forced, route, st);
+    case 1: return launch_flags_t<float, float>(A, B, flags, g, pf, forced, route, st);
+    default: return launch_flags_t<__half, float>(A, B, flags, g, pf, forced, route, st);
+    }
+}
+
+hipError_t launch_check_flags(const uint8_t *flags, int64_t n, double *bad, hipStream_t st) {
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, bad, 1, 0.0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(check_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flags, n, bad);
+    return hipGetLastError();
+}
+
+template <typename S, typename O>
+static hipError_t launch_macro_t(const void *A, const uint8_t *flags, void *rho, void *u, const Geom &g,
+                                 const double *F, hipStream_t st) {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL((macroscopic_kernel<S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
-                       (const S *)A, rho, u, g, F[0], F[1], F[2]);
+    hipLaunchKernelGGL((macroscopic_kernel<S, O>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       (const S *)A, flags, (O *)rho, (O *)u, g, F[0], F[1], F[2]);
     return hipGetLastError();
 }
 
-hipError_t launch_macroscopic(int storage, const void *A, double *rho, double *u, const Geom &g,
-                              const double *F, hipStream_t st) {
+template <typename O>
+static hipError_t launch_macro_o(int storage, const void *A, const uint8_t *flags, void *rho, void *u,
+                                 const Geom &g, const double *F, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_macro_t<double>(A, rho, u, g, F, st);
-    case 1: return launch_macro_t<float>(A, rho, u, g, F, st);
-    default: return launch_macro_t<__half>(A, rho, u, g, F, st);
+    case 0: return launch_macro_t<double, O>(A, flags, rho, u, g, F, st);
+    case 1: return launch_macro_t<float, O>(A, flags, rho, u, g, F, st);
+    default: return launch_macro_t<__half, O>(A, flags, rho, u, g, F, st);
     }
+}
+
+hipError_t launch_macroscopic(int storage, const void *A, const uint8_t *flags, void *rho, void *u, bool out_f32,
+                              const Geom &g, const double *F, hipStream_t st) {
+    return out_f32 ? launch_macro_o<float>(storage, A, flags, rho, u, g, F, st)
+                   : launch_macro_o<double>(storage, A, flags, rho, u, g, F, st);
 }
 
 template <typename S>
@@ -352,9 +480,9 @@ hipError_t launch_export(int storage, const void *A, double *f, const Geom &g, h
 }
 
 template <typename S>
-static hipError_t launch_reduce_t(const void *A, float *snap, int have_prev, const Geom &g, const double *F,
-                                  double *partials, int nblocks, double *out, hipStream_t st) {
-    hipLaunchKernelGGL((reduce_kernel<S>), dim3(nblocks), dim3(kReduceThreads), 0, st, (const S *)A, snap,
+static hipError_t launch_reduce_t(const void *A, const uint8_t *flags, double *snap, int have_prev, const Geom &g,
+                                  const double *F, double *partials, int nblocks, double *out, hipStream_t st) {
+    hipLaunchKernelGGL((reduce_kernel<S>), dim3(nblocks), dim3(kReduceThreads), 0, st, (const S *)A, flags, snap,
                        have_prev, g, F[0], F[1], F[2], partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -362,12 +490,12 @@ static hipError_t launch_reduce_t(const void *A, float *snap, int have_prev, con
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int storage, const void *A, float *snap, int have_prev, const Geom &g,
-                         const double *F, double *partials, int nblocks, double *out, hipStream_t st) {
+hipError_t launch_reduce(int storage, const void *A, const uint8_t *flags, double *snap, int have_prev,
+                         const Geom &g, const double *F, double *partials, int nblocks, double *out, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_reduce_t<double>(A, snap, have_prev, g, F, partials, nblocks, out, st);
-    case 1: return launch_reduce_t<float>(A, snap, have_prev, g, F, partials, nblocks, out, st);
-    default: return launch_reduce_t<__half>(A, snap, have_prev, g, F, partials, nblocks, out, st);
+    case 0: return launch_reduce_t<double>(A, flags, snap, have_prev, g, F, partials, nblocks, out, st);
+    case 1: return launch_reduce_t<float>(A, flags, snap, have_prev, g, F, partials, nblocks, out, st);
+    default: return launch_reduce_t<__half>(A, flags, snap, have_prev, g, F, partials, nblocks, out, st);
     }
 }
 

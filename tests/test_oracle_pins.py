@@ -324,6 +324,89 @@ def test_cavity_mass_and_mirror_symmetry():
     assert np.abs(u[0]).max() > 0.1 * U
 
 
+def _box_flags(nx, ny, nz, walls, lid=None):
+    """Flags of a lattice two nodes wider on every axis listed in `walls`
+    (0 x, 1 y, 2 z), whose outer layers there are solid; the outer layer on
+    the `lid` side (axis, +1 or -1) is a moving wall."""
+    shape = [nz, ny, nx]
+    for ax in walls:
+        shape[2 - ax] += 2
+    fl = np.zeros(shape, dtype=np.uint8)
+    for ax in walls:
+        idx = [slice(None)] * 3
+        for end in (0, -1):
+            idx[2 - ax] = end
+            fl[tuple(idx)] = oracle.WALL
+    if lid is not None:
+        ax, side = lid
+        idx = [slice(None)] * 3
+        idx[2 - ax] = -1 if side > 0 else 0
+        fl[tuple(idx)] = oracle.MOVING_WALL
+    return fl
+
+
+def _interior(a, walls):
+    idx = [slice(None)] * a.ndim
+    for ax in walls:
+        idx[a.ndim - 1 - ax] = slice(1, -1)
+    return a[tuple(idx)]
+
+
+def test_flagged_walls_reproduce_the_box():
+    """Half-way bounce-back at nodes flagged solid is the rule of the box
+    walls (Sec. 4.1, 4.3): a 7 x 6 x 5 cavity with its lid on +y equals, bit
+    for bit, the interior of a 9 x 8 x 7 lattice whose outer layers are
+    flagged solid, the +y layer moving (edges and corners included)."""
+    U = 0.05
+    box = W.cavity(6, U, 0.7, 50.0).with_(nx=7, ny=6, nz=5)
+    big = box.with_(nx=9, ny=8, nz=7, lid_face=W.LID_NONE)
+    fl = _box_flags(7, 6, 5, (0, 1, 2), lid=(1, +1))
+    f0 = W.perturbed_populations(box, 5, 1e-3).numpy()
+    g0 = np.broadcast_to(oracle.weights()[:, None, None, None], (Q, 7, 8, 9)).copy()
+    g0[:, 1:-1, 1:-1, 1:-1] = f0
+    f = oracle.run(box, f0, 40)
+    g = oracle.run(big, g0, 40, flags=fl)
+    assert np.array_equal(_interior(g, (0, 1, 2)), f)
+    # solid nodes keep the rest populations and report rho = 1, u = 0
+    w = oracle.weights()
+    assert np.array_equal(g[:, 0, 3, 3], w)
+    rho, u = oracle.macroscopic(big, g, flags=fl)
+    assert rho[0, 0, 0] == 1.0 and np.all(u[:, -1, :, :] == 0.0)
+
+
+def test_flagged_walls_reproduce_a_forced_channel():
+    """The same equivalence for a body-force-driven channel (walls on y,
+    periodic x and z) whose walls are flagged nodes."""
+    ch = W.config_poiseuille().with_(nx=4, ny=10, nz=3)
+    big = ch.with_(ny=12)
+    fl = _box_flags(4, 10, 3, (1,))
+    f0 = W.perturbed_populations(ch, 8, 1e-3).numpy()
+    g0 = np.broadcast_to(oracle.weights()[:, None, None, None], (Q, 3, 12, 4)).copy()
+    g0[:, :, 1:-1, :] = f0
+    f = oracle.run(ch, f0, 30)
+    g = oracle.run(big, g0, 30, flags=fl)
+    assert np.array_equal(_interior(g, (1,)), f)
+
+
+def test_flagged_obstacle_conserves_mass_and_mirror_symmetry():
+    """A solid block in a force-driven channel (periodic x and z, walls on y):
+    bounce-back at the block conserves mass exactly, the flow is mirror
+    symmetric about the channel's mid-plane (u_x even, u_y odd in y), it is
+    slowed behind the block, and the block reports no velocity."""
+    ch = W.LatticeSpec(nx=16, ny=12, nz=3, K=0.05, n=0.8, periodic=(1, 0, 1), force=(2e-5, 0.0, 0.0))
+    fl = np.zeros((3, 12, 16), dtype=np.uint8)
+    fl[:, 4:8, 5:8] = oracle.WALL
+    f = oracle.run(ch, W.rest_populations(ch).numpy(), 300, flags=fl)
+    rho, u = oracle.macroscopic(ch, f, flags=fl)
+    fluid = fl == 0
+    assert abs(rho[fluid].sum() - fluid.sum()) < 1e-12 * fluid.sum()
+    yflip = u[:, :, ::-1, :]
+    assert np.abs(u[0] - yflip[0]).max() < 1e-15
+    assert np.abs(u[1] + yflip[1]).max() < 1e-15
+    assert np.all(u[:, ~fluid] == 0.0)
+    assert u[0, 1, 5, 9] < 0.5 * u[0, 1, 5, 14]
+
+
 # ---------------------------------------------------------------------------
 # Flows with closed-form solutions
 # ---------------------------------------------------------------------------
