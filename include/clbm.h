@@ -251,6 +251,22 @@ clbm_status clbm_populations(clbm_lattice *h, double *f_dev, void *stream);
  * Returns CLBM_EUNSTABLE (after filling out) if out[5] > 0. */
 clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * reductions of clbm_reduce with no allocation, no host synchronization and
+ * no host copy: the eight values are written to out_dev (8 doubles of device
+ * memory owned by the caller) on `stream`, asynchronously; non-finite
+ * populations show in out_dev[5] (the call cannot return CLBM_EUNSTABLE).
+ * The residual uses and updates the same FP64 snapshot as clbm_reduce, and
+ * whether a previous velocity exists is decided when the call is made.  The
+ * block partials go to a static scratch array of the library (1024 blocks of
+ * 10 doubles plus 10, one copy per GPU, held until the process ends); a
+ * lattice needing more blocks is refused with EINVAL (none does: lattices
+ * are reduced with at most 1024 blocks).  Every call on one GPU shares that
+ * scratch, so calls that overlap on one GPU (two streams, or two threads)
+ * race; serialize them. */
+clbm_status clbm_reduce_noalloc(clbm_lattice *h, double *out_dev, void *stream);
+
 /* Index (0 = pop_a, 1 = pop_b; always 0 in the in-place form) of the buffer
  * holding the current state, and the number of steps taken since the last
  * init.  Either output may be NULL. */

@@ -82,6 +82,7 @@ SIGNATURES = {
     "clbm_macroscopic": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP]),
     "clbm_populations": (ctypes.c_int, [_VP, _VP, _VP]),
     "clbm_reduce": (ctypes.c_int, [_VP, _DP, _VP]),
+    "clbm_reduce_noalloc": (ctypes.c_int, [_VP, _VP, _VP]),
     "clbm_state": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int), _I64P]),
     "clbm_set_launch": (ctypes.c_int, [_VP, ctypes.POINTER(Launch)]),
     "clbm_get_launch": (ctypes.c_int, [_VP, ctypes.POINTER(Launch)]),
@@ -338,6 +339,13 @@ class Lattice:
             _check(rc)
         keys = ("mass", "momentum_x", "momentum_y", "momentum_z", "residual", "nonfinite", "umax", "kinetic")
         return dict(zip(keys, list(out)))
+
+    def reduce_noalloc(self, out: torch.Tensor, stream=None):
+        """clbm_reduce_noalloc: the eight reductions of reduce() written
+        asynchronously into `out` (a float64 device tensor of 8 values)."""
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 8 and out.is_contiguous()
+        _check(load().clbm_reduce_noalloc(self._h, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
 
     # -- launch shape ------------------------------------------------------
     def set_block(self, bx: int, by: int):

@@ -159,7 +159,7 @@ static clbm_status create_common(const clbm_params *p, void *pop_a, void *pop_b,
 
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     int64_t nb = (N + kReduceThreads - 1) / kReduceThreads;
-    h->nblocks = (int)(nb < 1024 ? nb : 1024);
+    h->nblocks = (int)(nb < kReduceMaxBlocks ? nb : kReduceMaxBlocks);
     hipError_t e = hipMalloc((void **)&h->partials, sizeof(double) * kReduceSlots * (h->nblocks + 1));
     if (e == hipSuccess) {
         h->result = h->partials + (size_t)kReduceSlots * h->nblocks;
@@ -357,6 +357,21 @@ clbm_status clbm_reduce(clbm_lattice *h, double out[8], void *stream) {
     out[7] = r[8];
     if (h->snapshot) h->have_snapshot = true;
     if (r[6] > 0.0) return fail(CLBM_EUNSTABLE, "%.0f nodes hold non-finite populations", r[6]);
+    return CLBM_OK;
+}
+
+clbm_status clbm_reduce_noalloc(clbm_lattice *h, double *out_dev, void *stream) {
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (!out_dev) return fail(CLBM_EINVAL, "out_dev is NULL");
+    if (!h->initialized) return fail(CLBM_ESTATE, "clbm_reduce_noalloc before an init call");
+    if (h->nblocks > kNoAllocMaxBlocks)
+        return fail(CLBM_EINVAL, "clbm_reduce_noalloc: %d reduction blocks exceed the static scratch of %d",
+                    h->nblocks, kNoAllocMaxBlocks);
+    const double F[3] = {h->prm.force[0], h->prm.force[1], h->prm.force[2]};
+    HIP_TRY(launch_reduce_noalloc(h->prm.storage, h->buf[h->cur], h->flags, h->snapshot, h->have_snapshot ? 1 : 0,
+                                  h->geom, output_force(h, F).data(), h->nblocks, out_dev, (hipStream_t)stream),
+            "clbm_reduce_noalloc");
+    if (h->snapshot) h->have_snapshot = true;
     return CLBM_OK;
 }
 

@@ -31,6 +31,10 @@ struct StepLaunch {
     int32_t fuse_planes;    // output z planes per two-step workgroup
 };
 constexpr int kReduceSlots = 10;
+// reduction blocks of a lattice: at most this many (grid-stride loop beyond)
+constexpr int kReduceMaxBlocks = 1024;
+// block partials the no-allocation reduction holds in its static scratch
+constexpr int kNoAllocMaxBlocks = 1024;
 
 hipError_t launch_step(int storage, const void *A, void *B, const Geom &g, const Relax<double> &pd,
                        const Relax<float> &pf, bool forced, int route, const StepLaunch &c, hipStream_t st);
@@ -74,5 +78,7 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 hipError_t launch_export(int storage, const void *A, double *f, const Geom &g, hipStream_t st);
 hipError_t launch_reduce(int storage, const void *A, const uint8_t *flags, double *snap, int have_prev,
                          const Geom &g, const double *F, double *partials, int nblocks, double *out, hipStream_t st);
+hipError_t launch_reduce_noalloc(int storage, const void *A, const uint8_t *flags, double *snap, int have_prev,
+                                 const Geom &g, const double *F, int nblocks, double *out, hipStream_t st);
 
 }  // namespace clbm

@@ -10,6 +10,8 @@
 //   export                f = w + stored deviation, as FP64
 //   reduce                FP64 block partials of mass, momentum, residual, NaNs
 //   reduce_final          fixed-order sum of the partials
+#include <mutex>
+
 #include "clbm_internal.hpp"
 
 namespace clbm {
@@ -274,6 +276,95 @@ reduce_final_kernel(const double *__restrict__ partials, int nblocks, double *__
         v = (k == 7) ? fmax(v, x) : v + x;
     }
     out[k] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Reduction without allocation: the block partials and the final sums live in
+// a file-scope device array, one copy per GPU, which the host reaches only
+// through the address hipGetSymbolAddress returns for the current device
+// (the array's name in host code is not a device address).  Every call on a
+// GPU shares that GPU's copy: calls that overlap on one GPU race.  The final
+// kernel writes the eight outputs of clbm_reduce to the caller's device
+// memory; nothing is copied to the host.
+// ---------------------------------------------------------------------------
+constexpr int kScratchDoubles = (kNoAllocMaxBlocks + 1) * kReduceSlots;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Device address of this GPU's scratch (looked up once per device, with that
+// device current).
+static hipError_t scratch_address(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Fixed-order sums of the partials (as reduce_final_kernel), then the eight
+// outputs of clbm_reduce: fluid mass, momentum, residual, non-finite count,
+// max |u|, kinetic energy.
+__global__ void __launch_bounds__(64)
+reduce_finish_kernel(const double *__restrict__ partials, int nblocks, int have_prev, double *__restrict__ sums,
+                     double *__restrict__ out) {
+    const int k = threadIdx.x;
+    if (k < kReduceSlots) {
+        double v = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            const double x = partials[(int64_t)b * kReduceSlots + k];
+            v = (k == 7) ? fmax(v, x) : v + x;
+        }
+        sums[k] = v;
+    }
+    __syncthreads();
+    if (k == 0) {
+        out[0] = sums[9] + sums[0];
+        out[1] = sums[1];
+        out[2] = sums[2];
+        out[3] = sums[3];
+        out[4] = (have_prev && sums[5] > 0.0) ? sqrt(sums[4] / sums[5]) : 0.0;
+        out[5] = sums[6];
+        out[6] = sums[7];
+        out[7] = sums[8];
+    }
+}
+
+template <typename S>
+static hipError_t launch_reduce_noalloc_t(const void *A, const uint8_t *flags, double *snap, int have_prev,
+                                          const Geom &g, const double *F, int nblocks, double *out,
+                                          hipStream_t st) {
+    double *ptr = nullptr;
+    hipError_t e = scratch_address(&ptr);
+    if (e != hipSuccess) return e;
+    double *sums = ptr + (size_t)kNoAllocMaxBlocks * kReduceSlots;
+    hipLaunchKernelGGL((reduce_kernel<S>), dim3(nblocks), dim3(kReduceThreads), 0, st, (const S *)A, flags, snap,
+                       have_prev, g, F[0], F[1], F[2], ptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_finish_kernel, dim3(1), dim3(64), 0, st, (const double *)ptr, nblocks,
+                       snap && have_prev ? 1 : 0, sums, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_noalloc(int storage, const void *A, const uint8_t *flags, double *snap, int have_prev,
+                                 const Geom &g, const double *F, int nblocks, double *out, hipStream_t st) {
+    if (nblocks < 1 || nblocks > kNoAllocMaxBlocks) return hipErrorInvalidValue;
+    switch (storage) {
+    case 0: return launch_reduce_noalloc_t<double>(A, flags, snap, have_prev, g, F, nblocks, out, st);
+    case 1: return launch_reduce_noalloc_t<float>(A, flags, snap, have_prev, g, F, nblocks, out, st);
+    default: return launch_reduce_noalloc_t<__half>(A, flags, snap, have_prev, g, F, nblocks, out, st);
+    }
 }
 
 // ---------------------------------------------------------------------------
