@@ -2,25 +2,32 @@
 """Throughput benchmark of the D3Q19 cascaded power-law stream-collide step.
 
 Workload (default): lid-driven cubic cavity 512^3 (134.2 M nodes), Re = 3200,
-n = 0.75, lid velocity 0.04, rest start, 5000 steps; FP32 storage of f - w
-with FP32 arithmetic; the FP64 mass reduction every 100 steps tracks the mass
-drift.  Each storage type runs in its faster launch form: FP32 two steps per
+n = 0.75, lid velocity 0.04, rest start; FP32 storage of f - w with FP32
+arithmetic; the FP64 mass reduction every 100 steps tracks the mass drift.
+Every timed run starts from rest and first takes --spinup untimed steps (1000
+by default), which set the whole cavity moving: from rest most nodes have no
+shear and skip the relaxation-rate solve, so steps timed near rest would be
+faster than the developed flow of the 5000-step run.  The first --rest-steps
+of the main run's spin-up are timed on their own and reported as a secondary
+figure.  Each storage type runs in its faster launch form: FP32 two steps per
 launch (temporal blocking, planes layout; one launch = two full steps of the
-fused pull stream-collide), FP16 deviations and FP64 one step per launch in
-the row-interleaved layout (a launch for the rows off the y and z faces and
-one for the face rows).  The FP16-deviation and FP64 runs end at the same
-step as the FP32 run, and the errors of FP32 and FP16 against FP64 are
-reported on the centrelines u_x(y), u_y(x) and normwise over the whole field.
+fused pull stream-collide), FP16 deviations (stochastic rounding) and FP64
+one step per launch in the row-interleaved layout (a launch for the rows off
+the y and z faces and one for the face rows).  All storage types run the same
+spin-up, warm-up and timed steps, and the errors of FP32 and FP16 against FP64
+are reported on the centrelines u_x(y), u_y(x) and normwise over the whole
+field.
 
 Prints ONE JSON line: MLUPS of the timed region (exactly --steps steps after
---warmup untimed ones, bracketed by device synchronisation), the roofline of
-the stream-collide kernel (algorithmic bytes of the steps a launch advances /
-average launch time measured with events on the launch stream), the other
-launch form and the planes layout of each storage type, the FP16-deviation
-and FP64 storage variants of the same workload, the 64-cavity batch
-(persistent graph-replayed launch vs one launch per instance), the
-achievable copy bandwidth, and the CPU oracle timed on the host cores on a
-bounded sample of the same workload.
+the spin-up and --warmup untimed ones, bracketed by device synchronisation),
+the roofline of the stream-collide kernel (algorithmic bytes of the steps a
+launch advances / average launch time measured with events on the launch
+stream, with the measured HBM traffic of the committed counter summary
+beside it), the other launch form and the planes layout of each storage
+type, the FP16-deviation and FP64 storage variants of the same workload, the
+64-cavity batch (persistent graph-replayed launch vs one launch per
+instance, with its roofline), the achievable copy bandwidth, and the CPU
+oracle timed on the host cores on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -123,17 +130,27 @@ def launch_of(form, storage, spec):
 
 
 def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=None, keep_u=False, launch=None,
-                 in_place=False, layout=None):
-    """Run warmup + timed steps; returns timing and reduction results (and
-    the final velocity field, FP64 on the device, if `keep_u`).  `launch`:
-    a launch dict (two steps per launch need the planes layout) or None."""
+                 in_place=False, layout=None, spinup=0, rest_steps=0):
+    """Rest start, then `spinup` untimed steps (the first `rest_steps` of them
+    timed on their own: the near-rest transient), `warmup` untimed steps, and
+    `steps` timed steps; returns timing and reduction results (and the final
+    velocity field, FP64 on the device, if `keep_u`).  `launch`: a launch
+    dict (two steps per launch need the planes layout) or None."""
     lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place, launch=launch,
                        layout=layout)
     lat.init_rest()
     r0 = lat.reduce()
-    lat.step(warmup)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    rest_ms = None
+    if rest_steps > 0:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(rest_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rest_ms = e0.elapsed_time(e1) / rest_steps
+    lat.step(max(spinup - rest_steps, 0) + warmup)
+    torch.cuda.synchronize()
     starts, ends = [], []
     t0 = time.perf_counter()
     done = 0
@@ -157,6 +174,7 @@ def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=
         "wall_s": wall,
         "ms_per_step": wall * 1e3 / steps,
         "kernel_ms_per_step": kernel_ms / steps,
+        "rest_kernel_ms_per_step": rest_ms,
         "mass_drift": (r1["mass"] - r0["mass"]) / r0["mass"],
         "umax": r1["umax"],
         "nonfinite": r1["nonfinite"],
@@ -172,42 +190,63 @@ def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=
     return out
 
 
-def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch, layout):
-    """HBM roofline of the stream-collide kernel: algorithmic bytes of one
-    launch (19 reads + 19 writes per node and step, times the steps one
-    launch advances) over the launch's average duration; `traffic` is the
-    measured HBM bytes per launch from the committed counter summary."""
+def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch, layout, kernel=None):
+    """HBM roofline of the stream-collide kernel: `achieved` is the
+    algorithmic bytes of one launch (19 reads + 19 writes per node and step,
+    times the steps one launch advances) over the launch's average duration;
+    `traffic` is the measured HBM bytes per launch from the committed counter
+    summary (null if absent or taken on other kernel sources), and
+    `hbm_gbs_measured` those bytes over the same duration."""
+    launch_ms = kernel_ms_per_step * steps_per_launch
     achieved = BYTES_PER_LUP[storage] * nodes / (kernel_ms_per_step * 1e-3) / 1e9
-    kernel = STEP_KERNEL[layout] if steps_per_launch == 1 else "stream_collide2"
+    if kernel is None:
+        kernel = STEP_KERNEL[layout] if steps_per_launch == 1 else "stream_collide2"
     traffic = measured_traffic(storage, workload, kernel)
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-           "bytes_per_lup": BYTES_PER_LUP[storage], "steps_per_launch": steps_per_launch}
+           "achieved_is": "algorithmic bytes per launch / launch time",
+           "bytes_per_lup": BYTES_PER_LUP[storage], "steps_per_launch": steps_per_launch,
+           "kernel_ms_per_launch": round(launch_ms, 4)}
     if traffic is not None:
         # measured HBM bytes over the algorithmic bytes of one launch (below 1: temporal blocking)
         out["traffic_over_algorithmic"] = round(traffic / (BYTES_PER_LUP[storage] * nodes * steps_per_launch), 3)
+        out["hbm_gbs_measured"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
     return out
 
 
-def batched(clbm, torch, W, storage, steps):
+BATCH_WORKLOAD = "batch64_cavities_L32-96_n0.4-1.6_re50-1000"
+
+
+def batched(clbm, torch, W, storage, steps, spinup):
     """The 64-cavity batch: one persistent launch per step (graph-replayed,
-    autotuned) against one launch per instance per step."""
+    autotuned after an untimed spin-up from rest) against one launch per
+    instance per step, both timed with events on the launch stream over
+    `steps` steps; the roofline of the persistent kernel in algorithmic bytes
+    per node update."""
     specs = W.config_batch()
     nodes = sum(s.nodes for s in specs)
     b = clbm.Batch(specs, storage=storage)
     b.init_rest()
-    b.step(10)
+    b.step(spinup)
     cfg, _ = b.autotune()
-    out = {"workload": "batch64_cavities_L32-96_n0.4-1.6_re50-1000", "instances": len(specs), "nodes": nodes,
-           "storage": storage, "steps": steps, "config": cfg}
+    out = {"workload": BATCH_WORKLOAD, "instances": len(specs), "nodes": nodes, "storage": storage,
+           "steps": steps, "spinup_steps": spinup, "config": cfg}
+    stream = torch.cuda.current_stream()
+    ms = {}
     for key, fn in (("mlups", b.step), ("mlups_one_launch_per_instance", b.step_each)):
         fn(10)
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record(stream)
         fn(steps)
+        e1.record(stream)
         torch.cuda.synchronize()
+        ms[key] = e0.elapsed_time(e1) / steps
         out[key] = round(nodes * steps / (time.perf_counter() - t0) / 1e6, 1)
     out["speedup"] = round(out["mlups"] / out["mlups_one_launch_per_instance"], 3)
+    kernel = "batch_packed" if cfg.get("passes", 0) > 0 else "batch_rows"
+    out["roofline"] = roofline(storage, nodes, ms["mlups"], BATCH_WORKLOAD, 1, "rows", kernel=kernel)
     r = b.reduce(raise_unstable=False)
     out["nonfinite_instances"] = sum(1 for x in r if x["nonfinite"] > 0)
     b.close()
@@ -216,12 +255,18 @@ def batched(clbm, torch, W, storage, steps):
     return out
 
 
-def accuracy_run(clbm, torch, spec, steps, report_every):
-    """The same cavity in FP64, FP32 and FP16-deviation storage from rest for
-    `steps` steps; errors of FP32 and FP16 against FP64 on the centrelines."""
+# storage variants of the accuracy runs: (name, storage, FP16 rounding)
+ACCURACY_VARIANTS = (("f64", "f64", "stochastic"), ("f32", "f32", "stochastic"), ("f16", "f16", "stochastic"),
+                     ("f16_nearest", "f16", "nearest"))
+
+
+def accuracy_run(clbm, torch, spec, steps, report_every, variants=ACCURACY_VARIANTS):
+    """The same cavity from rest for `steps` steps in FP64, FP32 and
+    FP16-deviation storage (stochastic and nearest-even rounding); errors of
+    each against FP64 on the centrelines and over the whole field."""
     fields, history = {}, {}
-    for st in ("f64", "f32", "f16"):
-        lat = clbm.Lattice(spec, storage=st, track_residual=True)
+    for key, st, rounding in variants:
+        lat = clbm.Lattice(spec, storage=st, track_residual=True, f16_rounding=rounding)
         lat.init_rest()
         m0 = lat.reduce()["mass"]
         t0 = time.perf_counter()
@@ -233,16 +278,41 @@ def accuracy_run(clbm, torch, spec, steps, report_every):
             r = lat.reduce(raise_unstable=False)
             hist.append({"step": done, "umax": r["umax"], "residual": r["residual"],
                          "mass_drift": (r["mass"] - m0) / m0, "nonfinite": r["nonfinite"]})
-            print(f"[accuracy] {spec.name} {st} step {done}: {time.perf_counter() - t0:.1f} s, "
+            print(f"[accuracy] {spec.name} {key} step {done}: {time.perf_counter() - t0:.1f} s, "
                   f"residual {r['residual']:.3e}, umax {r['umax']:.5f}", file=sys.stderr, flush=True)
-        fields[st] = lat.macroscopic()[1]
-        history[st] = hist[-1]
+        fields[key] = lat.macroscopic()[1]
+        history[key] = hist[-1]
         lat.close()
         del lat
         torch.cuda.empty_cache()
     out = accuracy_vs(torch, fields, "f64", spec.lid_velocity[0], spec.nx)
     out.update({"workload": spec.name, "steps": steps, "final": history})
-    return out
+    return out, fields
+
+
+def accuracy64(clbm, torch, W, steps=20000):
+    """The 64^3 cavity at Re 100 (n = 0.5, 1, 1.5), every storage variant
+    against GPU FP64 and, where the stored FP64 oracle results exist, against
+    them (the velocity on the mid-planes z = 31, 32 and every fourth node)."""
+    import numpy as np
+    out = []
+    for n in (0.5, 1.0, 1.5):
+        spec = W.config_cavity64(n)
+        acc, fields = accuracy_run(clbm, torch, spec, steps, 5000)
+        path = os.path.join(ROOT, "tests", "golden", f"cavity64_re100_n{n:g}_steps{steps}.npz")
+        if os.path.exists(path):
+            fx = np.load(path)
+            sub = slice(1, 64, 4)
+            ref = np.concatenate([fx["u_planes"].ravel(), fx["u_sub"].ravel()])
+            vs = {}
+            for key, u in fields.items():
+                uu = u.cpu().numpy()
+                got = np.concatenate([uu[:, [31, 32]].ravel(), uu[:, sub, sub, sub].ravel()])
+                vs[key] = float(f"{np.abs(got - ref).max() / np.abs(ref).max():.3e}")
+            acc["vs_stored_oracle"] = vs
+        out.append(acc)
+        print(json.dumps(acc), file=sys.stderr, flush=True)
+    return {"workload": "cavity64_re100, n = 0.5, 1, 1.5", "steps": steps, "runs": out}
 
 
 def stability(clbm, torch, W, steps=50000, check_every=5000):
@@ -279,6 +349,55 @@ def stability(clbm, torch, W, steps=50000, check_every=5000):
                       file=sys.stderr, flush=True)
             out.append(row)
     return {"workload": "cavity64, FP32, 50000 steps, bisection on U in (0, 0.4)", "rows": out}
+
+
+def stability_re(clbm, torch, W, steps=50000, check_every=5000, U=0.05, grids=(48, 64, 96, 128), iters=8,
+                 re_lo=10.0, re_hi=1.0e5):
+    """Largest stable Reynolds number against grid size (the first stability
+    protocol of Sec. 5): lid-driven cavity at a fixed lid velocity, the
+    consistency coefficient lowered (Re = H^n U^(2-n) / mu_p raised) until
+    the run becomes unstable, for the cascaded scheme and the BGK comparison
+    model.  Bisection on log Re in [re_lo, re_hi]; a probe is stable when the
+    state stays finite with max |u| below 1 for `steps` steps (checked every
+    `check_every`, the run stops at the first failure).  The viscosity clip
+    is opened to omega < 2 - 1e-6, as the protocol has none."""
+    import math
+    nu_min = (1.0 / (2.0 - 1e-6) - 0.5) / 3.0
+    out = []
+    for n in (0.8, 1.0, 1.5):
+        for L in grids:
+            row = {"n": n, "grid": L}
+            for model in ("cascaded", "srt"):
+                lo, hi = math.log(re_lo), math.log(re_hi)
+                stable_lo = None
+                for _ in range(iters):
+                    Re = math.exp(0.5 * (lo + hi))
+                    spec = W.cavity(L, U, n, Re).with_(nu_min=nu_min, model=model, name=f"stab{L}")
+                    lat = clbm.Lattice(spec, storage="f32", track_residual=False)
+                    lat.init_rest()
+                    ok, done = True, 0
+                    while done < steps:
+                        lat.step(check_every)
+                        done += check_every
+                        r = lat.reduce(raise_unstable=False)
+                        if r["nonfinite"] > 0 or not (r["umax"] < 1.0):
+                            ok = False
+                            break
+                    lat.close()
+                    del lat
+                    if ok:
+                        lo, stable_lo = math.log(Re), Re
+                    else:
+                        hi = math.log(Re)
+                    print(f"[stability-re] n={n} L={L} {model}: Re {Re:.1f} {'stable' if ok else 'unstable'} "
+                          f"({done} steps)", file=sys.stderr, flush=True)
+                row[model + "_max_Re"] = round(math.exp(lo), 1) if stable_lo is not None else None
+                row[model + "_unstable_Re"] = round(math.exp(hi), 1)
+            out.append(row)
+            torch.cuda.empty_cache()
+    return {"workload": f"lid-driven cavity, U = {U}, FP32, {steps} steps per probe, bisection on log Re in "
+                        f"[{re_lo:g}, {re_hi:g}] ({iters} probes), clip omega < 2 - 1e-6",
+            "rows": out}
 
 
 def copy_bandwidth(clbm, torch, nbytes=4 << 30, reps=10):
@@ -337,11 +456,12 @@ def main():
                     help="launch form of the main run and the storage variants: the faster one per storage type "
                          "(FP32 two steps per launch, FP16 and FP64 one), or one / two steps per launch for all")
     ap.add_argument("--reduce-every", type=int, default=100)
-    ap.add_argument("--variant-steps", type=int, default=-1,
-                    help="steps of the other storage variants (default: --steps + --warmup - 20, so that "
-                         "all storages end at the same step and their velocity fields are compared)")
-    ap.add_argument("--variant-warmup", type=int, default=20,
-                    help="untimed steps before the timed steps of the FP16/FP64 variants")
+    ap.add_argument("--spinup", type=int, default=1000,
+                    help="untimed steps from rest before the warm-up of every timed run: the lid sets the whole "
+                         "cavity moving, so the timed steps see the developed flow (from rest most nodes have no "
+                         "shear and skip the relaxation-rate solve)")
+    ap.add_argument("--rest-steps", type=int, default=100,
+                    help="the first steps of the main run's spin-up, timed on their own (secondary figure)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
@@ -353,9 +473,17 @@ def main():
     ap.add_argument("--stability", action="store_true",
                     help="instead of the benchmark: largest stable lid velocity of the 64^3 cavity, cascaded "
                          "scheme vs the single-relaxation-time comparison model")
+    ap.add_argument("--stability-re", action="store_true",
+                    help="instead of the benchmark: largest stable Re against grid size (48^3 .. 128^3), cascaded "
+                         "scheme vs the single-relaxation-time comparison model")
     ap.add_argument("--accuracy256", type=int, default=0, metavar="STEPS",
                     help="instead of the benchmark: run the 256^3 cavity (Re 1000, n 0.5) for STEPS steps in "
                          "FP64, FP32 and FP16-deviation storage and print the centreline errors vs FP64")
+    ap.add_argument("--accuracy64", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: the 64^3 cavity (Re 100, n = 0.5, 1, 1.5) for STEPS steps in "
+                         "every storage variant, errors vs GPU FP64 and vs the stored oracle results")
+    ap.add_argument("--accuracy512", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: the 512^3 cavity for STEPS steps in every storage variant")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -374,34 +502,50 @@ def main():
     if args.stability:
         print(json.dumps(stability(clbm, torch, W)), flush=True)
         return
+    if args.stability_re:
+        print(json.dumps(stability_re(clbm, torch, W)), flush=True)
+        return
     if args.accuracy256:
-        print(json.dumps(accuracy_run(clbm, torch, W.config_cavity256(), args.accuracy256, 5000)), flush=True)
+        print(json.dumps(accuracy_run(clbm, torch, W.config_cavity256(), args.accuracy256, 5000)[0]), flush=True)
+        return
+    if args.accuracy64:
+        print(json.dumps(accuracy64(clbm, torch, W, args.accuracy64)), flush=True)
+        return
+    if args.accuracy512:
+        print(json.dumps(accuracy_run(clbm, torch, W.config_cavity512(), args.accuracy512, 1000)[0]), flush=True)
         return
     spec = W.config_cavity512() if args.size == 512 else \
         W.cavity(args.size, 0.04, 0.75, 3200.0, name=f"cavity{args.size}_re3200_n0.75")
     workload = spec.name
-
-    compare = not args.no_variants and args.variant_steps < 0
-    vsteps = args.steps + args.warmup - args.variant_warmup if args.variant_steps < 0 else args.variant_steps
+    spin = args.spinup
+    compare = not args.no_variants
 
     def form_of(st):
         return BEST_FORM[st] if args.form == "best" else args.form
 
-    def run_form(st, form, steps, warmup, keep_u=False):
+    def run_form(st, form, steps, warmup, keep_u=False, rest_steps=0):
         launch = launch_of(form, st, spec)
         return time_lattice(clbm, torch, spec, st, steps, warmup, args.reduce_every, keep_u=keep_u, launch=launch,
-                            layout="planes" if launch else args.layout)
+                            layout="planes" if launch else args.layout, spinup=spin, rest_steps=rest_steps)
 
-    main_run = run_form(args.storage, form_of(args.storage), args.steps, args.warmup, keep_u=compare)
+    def frac_of(st, ms):
+        return round(BYTES_PER_LUP[st] * spec.nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    rest_steps = min(args.rest_steps, spin)
+    main_run = run_form(args.storage, form_of(args.storage), args.steps, args.warmup, keep_u=compare,
+                        rest_steps=rest_steps)
     mlups = spec.nodes * args.steps / (main_run["ms_per_step"] * args.steps * 1e-3) / 1e6
+    print(f"[bench] main run {args.storage}: {main_run['kernel_ms_per_step']:.4f} ms/step in the developed flow",
+          file=sys.stderr, flush=True)
 
+    # every storage runs the same spin-up, warm-up and timed steps, so all end at the same step
     variants = {}
     fields = {args.storage: main_run.pop("u", None)}
     if not args.no_variants:
         for st in ("f16", "f64", "f32"):
             if st == args.storage:
                 continue
-            r = run_form(st, form_of(st), vsteps, args.variant_warmup, keep_u=compare)
+            r = run_form(st, form_of(st), args.steps, args.warmup, keep_u=compare)
             fields[st] = r.pop("u", None)
             spl = r["launch"]["fuse_steps"]
             variants[st] = {
@@ -409,43 +553,40 @@ def main():
                 "roofline": roofline(st, spec.nodes, r["kernel_ms_per_step"], workload, spl, r["layout"]),
                 "kernel_ms_per_launch": round(r["kernel_ms_per_step"] * spl, 4),
                 "steps_per_launch": spl,
-                "mass_drift": r["mass_drift"], "steps": vsteps,
+                "mass_drift": r["mass_drift"], "steps": args.steps,
             }
-    # the other launch form of each storage (one vs two steps per launch)
+            print(f"[bench] variant {st}: {r['kernel_ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+    # the other launch form of each storage (one vs two steps per launch), after the same spin-up
     launch_forms = {}
     if not (args.no_variants or args.no_extras):
         for st in ("f32", "f64", "f16"):
             r = run_form(st, "one" if form_of(st) == "two" else "two", 300, 20)
-            spl = r["launch"]["fuse_steps"]
             launch_forms[st] = {
                 "launch": r["launch"], "layout": r["layout"],
                 "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
                 "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
-                "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
-                                       / HBM_PEAK_GBS, 4)}
+                "roofline_frac": frac_of(st, r["kernel_ms_per_step"])}
 
     # the planes layout, one step per launch, for each storage
     planes_layout = {}
     if not (args.no_variants or args.no_extras):
         for st in ("f32", "f16", "f64"):
-            r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, layout="planes")
+            r = time_lattice(clbm, torch, spec, st, 300, 20, args.reduce_every, layout="planes", spinup=spin)
             planes_layout[st] = {
                 "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
                 "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
-                "roofline_frac": round(BYTES_PER_LUP[st] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3) / 1e9
-                                       / HBM_PEAK_GBS, 4)}
+                "roofline_frac": frac_of(st, r["kernel_ms_per_step"])}
 
-    # the library's autotuner on the same workload (FP32, row layout, after a short warm-up)
+    # the library's autotuner on the same workload (FP32, row layout, after the spin-up)
     autotuned = None
     if not (args.no_variants or args.no_extras):
         lat = clbm.Lattice(spec, storage="f32", track_residual=False)
         lat.init_rest()
-        lat.step(20)
+        lat.step(spin)
         default = lat.get_launch()
         cfg, ms = lat.autotune()
         autotuned = {"storage": "f32", "default_launch": default, "best_launch": cfg,
-                     "best_ms_per_step": round(ms, 4),
-                     "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                     "best_ms_per_step": round(ms, 4), "roofline_frac": frac_of("f32", ms)}
         lat.close()
         del lat
         torch.cuda.empty_cache()
@@ -453,27 +594,26 @@ def main():
     # the single-relaxation-time comparison model on the same workload (FP32)
     comparison = None
     if not (args.no_variants or args.no_extras):
-        r = time_lattice(clbm, torch, spec.with_(model="srt"), "f32", 300, 20, args.reduce_every)
-        comparison = {"model": "single-relaxation-time (BGK), same power law, FP32, 300 steps",
+        r = time_lattice(clbm, torch, spec.with_(model="srt"), "f32", 300, 20, args.reduce_every, spinup=spin)
+        comparison = {"model": "single-relaxation-time (BGK), same power law, FP32, 300 steps after the spin-up",
                       "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
                       "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
-                      "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3)
-                                             / 1e9 / HBM_PEAK_GBS, 4)}
+                      "roofline_frac": frac_of("f32", r["kernel_ms_per_step"])}
 
     # one state buffer, stepped in place (AA pattern), FP32
     in_place = None
     if not (args.no_variants or args.no_extras):
-        r = time_lattice(clbm, torch, spec, "f32", 300, 20, args.reduce_every, in_place=True)
+        r = time_lattice(clbm, torch, spec, "f32", 300, 20, args.reduce_every, in_place=True, spinup=spin)
         in_place = {"storage": "f32", "steps": 300, "mlups": round(spec.nodes / (r["ms_per_step"] * 1e-3) / 1e6, 1),
                     "kernel_ms_per_step": round(r["kernel_ms_per_step"], 4),
-                    "roofline_frac": round(BYTES_PER_LUP["f32"] * spec.nodes / (r["kernel_ms_per_step"] * 1e-3)
-                                           / 1e9 / HBM_PEAK_GBS, 4),
+                    "roofline_frac": frac_of("f32", r["kernel_ms_per_step"]),
                     "state_bytes": 1 * 19 * spec.nodes * 4}
 
     accuracy = None
     if compare:
         accuracy = accuracy_vs(torch, fields, "f64", spec.lid_velocity[0], args.size)
-        accuracy["steps"] = args.steps + args.warmup
+        accuracy["steps"] = spin + args.warmup + args.steps
+        accuracy["f16_rounding"] = "stochastic"
     del fields
     torch.cuda.empty_cache()
 
@@ -492,11 +632,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "nodes": spec.nodes, "storage": args.storage,
                    "lid_velocity": spec.lid_velocity[0], "Re": 3200.0, "n": spec.n, "K": spec.K,
-                   "init": "rest", "reduce_every": args.reduce_every, "layout": main_run["layout"],
+                   "init": "rest", "spinup_steps": spin,
+                   "timed": f"{args.steps} steps after {spin} untimed spin-up steps from rest (the whole cavity "
+                            f"moving) and {args.warmup} warm-up steps",
+                   "reduce_every": args.reduce_every, "layout": main_run["layout"],
                    "launch": main_run["launch"]},
         "roofline": roofline(args.storage, spec.nodes, main_run["kernel_ms_per_step"], workload,
                              main_run["launch"]["fuse_steps"], main_run["layout"]),
         "kernel_ms_per_launch": round(main_run["kernel_ms_per_step"] * main_run["launch"]["fuse_steps"], 4),
+        "rest_start": None if main_run["rest_kernel_ms_per_step"] is None else {
+            "steps": rest_steps, "kernel_ms_per_step": round(main_run["rest_kernel_ms_per_step"], 4),
+            "roofline_frac": frac_of(args.storage, main_run["rest_kernel_ms_per_step"]),
+            "note": "the first steps from rest, most of the cavity still at rest (secondary figure)"},
         "mass_drift": main_run["mass_drift"],
         "variants": variants,
         "other_launch_form": launch_forms,
@@ -507,7 +654,7 @@ def main():
         "accuracy": accuracy,
     }
     if not args.no_batch:
-        line["batched"] = batched(clbm, torch, W, "f32", args.batch_steps)
+        line["batched"] = batched(clbm, torch, W, "f32", args.batch_steps, spin)
     if not args.no_copy:
         line["copy_gbs"] = round(copy_bandwidth(clbm, torch), 1)
     if not args.no_cpu:

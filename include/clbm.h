@@ -32,7 +32,8 @@
  *     f_alpha - w_alpha of the post-collision population (pre-collision in
  *     the one-buffer form of clbm_create_in_place) from the rest
  *     weight w = (1/3, 1/18 x 6, 1/36 x 12), stored as double (CLBM_F64),
- *     float (CLBM_F32) or IEEE half (CLBM_F16_DEV, round to nearest even).
+ *     float (CLBM_F32) or IEEE half (CLBM_F16_DEV, rounded as
+ *     clbm_params.f16_rounding says).
  *     Arithmetic is double for CLBM_F64 and float otherwise.
  *   - State buffers and pools must be 256-byte aligned device memory owned
  *     by the caller.  The library never frees caller memory.  It allocates a
@@ -101,6 +102,16 @@ typedef enum {
     CLBM_LID_PY = 4, CLBM_LID_MZ = 5, CLBM_LID_PZ = 6
 } clbm_lid_face;
 
+/* Rounding of the FP16 state.  Stochastic (default): each stored collision
+ * result is rounded up or down at random, with the probability that makes
+ * the expected stored value equal to the FP32 result, so rounding errors do
+ * not repeat from step to step (round-to-nearest of a slowly changing value
+ * repeats the same error every step, a bias that accumulates in the flow).
+ * The random bits are a counter-based hash of (node, direction, collision
+ * index): results are reproducible and do not depend on the launch form,
+ * layout or block shape.  Nearest even: IEEE round-to-nearest-even. */
+typedef enum { CLBM_F16_STOCHASTIC = 0, CLBM_F16_NEAREST_EVEN = 1 } clbm_f16_rounding;
+
 /* Per-node flag values of the optional flag array of clbm_create: a fluid
  * node is updated by the scheme; a link from a fluid node to a wall node is
  * closed by half-way bounce-back (Sec. 4.1), and to a moving-wall node by
@@ -124,7 +135,8 @@ typedef struct {
                                   clbm_buffer_size); unused in the row layout */
     int32_t collision;         /* clbm_collision: which algebraic form of the collision runs */
     int32_t layout;            /* clbm_layout of the state buffers */
-    int32_t reserved;          /* must be 0 */
+    int32_t f16_rounding;      /* CLBM_F16_DEV storage: how collision results are rounded to FP16
+                                  (clbm_f16_rounding); ignored for the other storage types */
     double K;                  /* consistency coefficient mu_p > 0 (Eq. 5) */
     double n;                  /* power-law index n > 0 (Eq. 5; n = 1 Newtonian) */
     double nu_min, nu_max;     /* clip of the apparent kinematic viscosity mu/rho,
@@ -331,9 +343,10 @@ const char *clbm_last_error(void);
  * hipGraph and replayed.  All instances share the storage type and the
  * layout (EINVAL otherwise).  Instance i occupies clbm_buffer_size bytes of
  * its params, rounded up to 256, at a 256-byte-aligned offset of each pool, in
- * instance order.  Row layout: each wave takes (instance, row, run of 64 x)
- * items; planes: each workgroup takes (instance, z layer, run of bx nodes)
- * tiles.
+ * instance order.  Row layout: each wave takes (instance, z layer, k passes
+ * of 64 consecutive nodes) items, or (instance, row, run of 64 x) items;
+ * planes: each workgroup takes (instance, z layer, run of bx nodes) tiles.
+ * Row-layout instances hold less than 2 GiB of state each.
  * ------------------------------------------------------------------------ */
 typedef struct clbm_batch clbm_batch;
 
@@ -346,6 +359,9 @@ typedef struct {
     int32_t nt_stores;         /* 1: non-temporal (streaming) stores, 0: plain stores (default: the
                                   short runs of small lattices leave partial cache lines, which plain
                                   stores let the cache merge) */
+    int32_t passes;            /* row layout: 0 = each wave item is one row's run of 64 x; k > 0 = each
+                                  item is k passes of 64 consecutive nodes of a z layer (rows packed
+                                  into whole waves; default 4); planes layout: must be 0 */
 } clbm_batch_config;
 
 /* Bytes each of the two pools must hold for these instances. */
@@ -404,6 +420,14 @@ clbm_status clbm_batch_destroy(clbm_batch *b);
  * calibration of hardware byte counters against a kernel of known traffic.
  * Asynchronous on `stream`. */
 clbm_status clbm_copy_probe(const void *src, void *dst, size_t bytes, void *stream);
+
+/* Test utility: the rounding of FP32 values to the FP16 state on its own.
+ * in: n floats, seeds: n random words (stochastic mode), out: n IEEE half
+ * bit patterns; device memory; mode: clbm_f16_rounding.  Asynchronous.
+ * The step kernels apply exactly this conversion to every stored collision
+ * result, with seeds from the hash described at clbm_f16_rounding. */
+clbm_status clbm_f16_round(const float *in, const uint32_t *seeds, uint16_t *out, int64_t n, int32_t mode,
+                           void *stream);
 
 /* Version string and the lattice tables compiled into the kernels (for
  * tests): e[3*alpha + c], opposite[alpha], w[alpha]. */

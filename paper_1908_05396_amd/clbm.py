@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("plane_pad", ctypes.c_int32),
         ("collision", ctypes.c_int32),
         ("layout", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("f16_rounding", ctypes.c_int32),
         ("K", ctypes.c_double), ("n", ctypes.c_double),
         ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
         ("omega_bulk", ctypes.c_double),
@@ -62,7 +62,7 @@ class Launch(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("nt_stores", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("nt_stores", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
 
 _lib = None
@@ -94,6 +94,7 @@ SIGNATURES = {
     "clbm_version": (ctypes.c_char_p, []),
     "clbm_lattice_tables": (ctypes.c_int, [_I32P, _I32P, _DP]),
     "clbm_copy_probe": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
+    "clbm_f16_round": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP]),
     "clbm_batch_size": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "clbm_batch_create": (ctypes.c_int, [_PP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, ctypes.c_char_p,
                                          ctypes.POINTER(_VP)]),
@@ -164,8 +165,29 @@ def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None):
     return nbytes
 
 
+F16_ROUNDING = {"stochastic": 0, "nearest": 1}
+
+
+def f16_round(x: torch.Tensor, seeds: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """The library's FP16 rounding of float32 device values: stochastic with
+    the given uint32 seeds (stored as int32), or nearest even if seeds is
+    None.  Returns float16."""
+    x = x.contiguous()
+    assert x.is_cuda and x.dtype == torch.float32
+    out = torch.empty(x.shape, dtype=torch.float16, device=x.device)
+    mode = 1 if seeds is None else 0
+    sp = None
+    if seeds is not None:
+        seeds = seeds.contiguous()
+        assert seeds.is_cuda and seeds.dtype == torch.int32 and seeds.numel() == x.numel()
+        sp = ctypes.c_void_p(seeds.data_ptr())
+    _check(load().clbm_f16_round(ctypes.c_void_p(x.data_ptr()), sp, ctypes.c_void_p(out.data_ptr()),
+                                 int(x.numel()), mode, _stream(stream)))
+    return out
+
+
 def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, plane_pad: int = -1,
-                     collision: str = "auto", layout: str = "rows") -> Params:
+                     collision: str = "auto", layout: str = "rows", f16_rounding: str = "stochastic") -> Params:
     """Fill the C parameter struct from a problem description with the
     attributes of workloads.LatticeSpec."""
     p = Params()
@@ -184,6 +206,7 @@ def params_from_spec(spec, storage: str = "f32", track_residual: bool = True, pl
         collision = "srt"
     p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     p.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)
+    p.f16_rounding = F16_ROUNDING[f16_rounding] if isinstance(f16_rounding, str) else int(f16_rounding)
     p.K, p.n = float(spec.K), float(spec.n)
     p.nu_min, p.nu_max = float(spec.nu_min), float(spec.nu_max)
     p.omega_bulk = float(spec.omega_bulk)
@@ -212,7 +235,8 @@ class Lattice:
 
     def __init__(self, spec, storage: str = "f32", device="cuda", track_residual: bool = True,
                  block=None, plane_pad: int = -1, launch: dict = None, collision: str = "auto",
-                 in_place: bool = False, layout: str = None, flags: torch.Tensor = None):
+                 in_place: bool = False, layout: str = None, flags: torch.Tensor = None,
+                 f16_rounding: str = "stochastic"):
         """layout: "rows" or "planes"; None picks planes for two steps per
         launch (which need them), rows otherwise.  flags: optional uint8
         tensor of shape (nz, ny, nx) with CLBM_FLUID / CLBM_WALL /
@@ -226,7 +250,7 @@ class Lattice:
             two_step = bool(launch) and int(launch.get("fuse_steps", 1)) == 2
             layout = "planes" if two_step else "rows"
         self.layout = layout
-        self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision, layout)
+        self.params = params_from_spec(spec, storage, track_residual, plane_pad, collision, layout, f16_rounding)
         self.plane, self.nbytes = buffer_size(self.params)
         self.device = torch.device(device)
         nbuf = 1 if self.in_place else 2
@@ -382,7 +406,8 @@ class Batch:
     stepped together by the batched persistent launch."""
 
     def __init__(self, specs, storage: str = "f32", device="cuda", track_residual: bool = False,
-                 tune_cache: str = None, collision: str = "auto", layout: str = "rows"):
+                 tune_cache: str = None, collision: str = "auto", layout: str = "rows",
+                 f16_rounding: str = "stochastic"):
         lib = load()
         self.specs = list(specs)
         self.storage = storage
@@ -390,7 +415,7 @@ class Batch:
         n = len(self.specs)
         arr = (Params * n)()
         for i, sp in enumerate(self.specs):
-            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision, layout)
+            arr[i] = params_from_spec(sp, storage, track_residual, -1, collision, layout, f16_rounding)
         self._params = arr
         nbytes = ctypes.c_size_t()
         _check(lib.clbm_batch_size(arr, n, ctypes.byref(nbytes)))

@@ -49,6 +49,12 @@ static std::array<double, 3> output_force(const clbm_lattice *h, const double F[
     return {s * F[0], s * F[1], s * F[2]};
 }
 
+// Index of the next collision (0: the initial one), which keys the stochastic
+// rounding of FP16 storage.
+static void set_step(clbm_lattice *h, int64_t step) {
+    h->rd.step = h->rf.step = (uint32_t)step;
+}
+
 static void default_fusion(const clbm_params *p, StepLaunch *c) {
     const bool f64 = p->storage == CLBM_F64;
     c->fuse_steps = 1;
@@ -81,6 +87,17 @@ clbm_status clbm_copy_probe(const void *src, void *dst, size_t bytes, void *stre
     if (bytes % 16 != 0 || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
         return fail(CLBM_EINVAL, "copy probe: bytes and pointers must be multiples of 16");
     HIP_TRY(launch_copy_probe(src, dst, bytes, (hipStream_t)stream), "clbm_copy_probe");
+    return CLBM_OK;
+}
+
+clbm_status clbm_f16_round(const float *in, const uint32_t *seeds, uint16_t *out, int64_t n, int32_t mode,
+                           void *stream) {
+    if (n < 0) return fail(CLBM_EINVAL, "f16 round: n must be >= 0");
+    if (mode != CLBM_F16_STOCHASTIC && mode != CLBM_F16_NEAREST_EVEN)
+        return fail(CLBM_EINVAL, "f16 round: unknown mode %d", mode);
+    if (n > 0 && (!in || !out || (mode == CLBM_F16_STOCHASTIC && !seeds)))
+        return fail(CLBM_EINVAL, "f16 round: NULL pointer");
+    HIP_TRY(launch_f16_round(in, seeds, out, n, mode == CLBM_F16_STOCHASTIC, (hipStream_t)stream), "clbm_f16_round");
     return CLBM_OK;
 }
 
@@ -232,6 +249,7 @@ clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, int on_devi
         src = staged;
     }
     h->cur = 0;
+    set_step(h, 0);
     hipError_t e = h->in_place ? launch_store_plain(h->prm.storage, src, h->buf[0], h->geom, st)
                                : launch_init(h->prm.storage, src, h->buf[0], h->flags, h->geom, h->rd, h->rf,
                                              h->forced, h->route, st);
@@ -250,6 +268,7 @@ clbm_status clbm_init_populations(clbm_lattice *h, const double *f0, int on_devi
 clbm_status clbm_init_rest(clbm_lattice *h, void *stream) {
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
     h->cur = 0;
+    set_step(h, 0);
     // f = w: every deviation is zero; the two-buffer form collides that state once
     if (h->in_place)
         HIP_TRY(launch_store_plain(h->prm.storage, nullptr, h->buf[0], h->geom, (hipStream_t)stream),
@@ -273,6 +292,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
         if (nsteps % 2) return fail(CLBM_EINVAL, "in-place lattices advance by even step counts (got %lld)",
                                     (long long)nsteps);
         for (int64_t t = 0; t < nsteps; t += 2) {
+            set_step(h, h->steps_done + 1);
             HIP_TRY(launch_aa_pair(h->prm.storage, h->buf[0], h->geom, h->rd, h->rf, h->forced, h->route,
                                    h->launch, st),
                     "clbm_step (in place)");
@@ -282,6 +302,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     }
     if (h->flags) {
         for (int64_t t = 0; t < nsteps; ++t) {
+            set_step(h, h->steps_done + 1);
             HIP_TRY(launch_step_flags(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->flags, h->geom, h->rd,
                                       h->rf, h->forced, h->route, st),
                     "clbm_step (flagged lattice)");
@@ -293,6 +314,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
     int64_t t = 0;
     if (h->launch.fuse_steps == 2) {
         for (; t + 2 <= nsteps; t += 2) {
+            set_step(h, h->steps_done + 1);
             HIP_TRY(launch_step2(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf,
                                  h->forced, h->route, h->launch, st),
                     "clbm_step (two-step launch)");
@@ -301,6 +323,7 @@ clbm_status clbm_step(clbm_lattice *h, int64_t nsteps, void *stream) {
         }
     }
     for (; t < nsteps; ++t) {
+        set_step(h, h->steps_done + 1);
         if (h->geom.rows)
             HIP_TRY(launch_step_rows(h->prm.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geom, h->rd, h->rf,
                                      h->forced, h->route, h->launch, st),

@@ -25,15 +25,23 @@ template <typename T> struct BatchInst {
     Relax<T> p;
     int64_t base;       // element offset of the instance's state in each pool
     uint32_t tile0;     // first tile of the instance in the flattened list
-    uint32_t chunks;    // tiles per z layer (planes) or 64-wide runs per row (rows)
+    uint32_t chunks;    // tiles per z layer (planes), 64-wide runs per row (rows), or packed items per z
+                        // layer (rows, packed)
     float inv_nx;       // 1 / nx, for the row of a node within a layer
     int32_t forced;
+    uint32_t bytes;     // bytes of the instance's state (row layout, packed items)
 };
 
+// The collision index of a launch (it keys the stochastic rounding of FP16
+// storage) is *step_base + step_off: step_base is set on the stream before
+// each run of launches, step_off is the launch's place in that run, so that
+// launches captured in a graph draw new rounding bits on every replay.
 template <typename S, typename T, int Route, int StAux>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
-                  const int32_t *__restrict__ tile_inst, uint32_t ntiles) {
+                  const int32_t *__restrict__ tile_inst, uint32_t ntiles, const uint32_t *__restrict__ step_base,
+                  uint32_t step_off) {
+    const uint32_t step = *step_base + step_off;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int i = tile_inst[t];
         const Geom g = inst[i].g;
@@ -56,23 +64,27 @@ batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
             collide<T, true, Route, NewtonSteps<S>::value>(d, p, nullptr);
         else
             collide<T, false, Route, NewtonSteps<S>::value>(d, p, nullptr);
+        round_state<S, T>(d, p, self, step);
 #pragma unroll
         for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B + base, g, a, self, d[a]);
     }
 }
 
 template <typename S, typename T, bool Forced, int Route, int StAux>
-__device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T> &p, int x, int y, int z) {
+__device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T> &p, int x, int y, int z,
+                                 uint32_t step) {
     if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1)
-        row_step<S, T, Forced, 0, StAux, Route, true>(A, B, g, p, x, y, z);
+        row_step<S, T, Forced, 0, StAux, Route, true>(A, B, g, p, x, y, z, step);
     else
-        row_step<S, T, Forced, 0, StAux, Route, false>(A, B, g, p, x, y, z);
+        row_step<S, T, Forced, 0, StAux, Route, false>(A, B, g, p, x, y, z, step);
 }
 
 template <typename S, typename T, int Route, int StAux>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
-                  const int32_t *__restrict__ tile_inst, uint32_t ntiles) {
+                  const int32_t *__restrict__ tile_inst, uint32_t ntiles, const uint32_t *__restrict__ step_base,
+                  uint32_t step_off) {
+    const uint32_t step = __builtin_amdgcn_readfirstlane(*step_base + step_off);
     const uint32_t waves = blockDim.x >> 6;
     const uint32_t w0 = blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63u);
@@ -88,47 +100,176 @@ batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         if (x >= g.nx) continue;
         const Relax<T> &p = inst[i].p;
         if (inst[i].forced)
-            batch_row<S, T, true, Route, StAux>(A + base, B + base, g, p, x, y, z);
+            batch_row<S, T, true, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
         else
-            batch_row<S, T, false, Route, StAux>(A + base, B + base, g, p, x, y, z);
+            batch_row<S, T, false, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
+    }
+}
+
+struct BatchStep {
+    const uint32_t *base;   // device: collision index before the first launch of the run
+    uint32_t off;           // this launch's place in the run (1, 2, ...)
+};
+
+// ---------------------------------------------------------------------------
+// Packed items (row layout): a wave takes `passes` passes of 64 consecutive
+// nodes of one z layer, so a pass may hold the ends and starts of several
+// rows and a lattice of any width fills whole waves.  Each lane addresses its
+// own row through one buffer descriptor per instance (byte offset of element
+// (19 r + a) nx + x); the offset of direction a's source is the lane's offset
+// plus a uniform constant.  A pass whose lanes all lie off the y and z faces
+// takes that uniform pull, with the x-face lanes redone; a pass touching a
+// face row takes the full wall rule per lane.  Consecutive passes of a layer
+// stay in one wave, so the cache lines two neighbouring rows share are read
+// and written by the same wave.
+// ---------------------------------------------------------------------------
+template <typename S, typename T, bool Forced, int Route, int StAux>
+__device__ inline void packed_pass(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p,
+                                   uint32_t bytes, float inv_nx, uint32_t l, int z, uint32_t step) {
+    constexpr int es = (int)sizeof(S);
+    const bool active = l < (uint32_t)g.nxy;
+    // row y = l / nx: float estimate, corrected to the exact quotient (l < 2^22)
+    int y = (int)((float)l * inv_nx);
+    if ((uint32_t)y * (uint32_t)g.nx > l) --y;
+    if ((uint32_t)(y + 1) * (uint32_t)g.nx <= l) ++y;
+    const int x = (int)(l - (uint32_t)y * (uint32_t)g.nx);
+    const bool face = y == 0 || y >= g.ny - 1 || z == 0 || z == g.nz - 1;
+    const bool any_face = __any(active && face);
+    if (!active) return;
+    const __amdgpu_buffer_rsrc_t ra = row_rsrc(A, __builtin_amdgcn_readfirstlane(bytes));
+    const __amdgpu_buffer_rsrc_t rb = row_rsrc(B, __builtin_amdgcn_readfirstlane(bytes));
+    const int nx = g.nx, ny = g.ny;
+    const int lane_el = (Q * (y + ny * z)) * nx + x;             // element of (a = 0, x) in the row group
+    auto own = [&](int a) { return (T)RawBits<S>::template load<0>(ra, (uint32_t)((lane_el + opp(a) * nx) * es)); };
+    T d[Q];
+    if (!any_face) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const int c = (a - Q * cy(a) - Q * cz(a) * ny) * nx - cx(a);
+            d[a] = (T)RawBits<S>::template load<0>(ra, (uint32_t)((lane_el + c) * es));
+        }
+        if (x == 0 || x == nx - 1) {
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                if (!((x == 0 && cx(a) == 1) || (x == nx - 1 && cx(a) == -1))) continue;
+                if (g.px) {
+                    const int c = (a - Q * cy(a) - Q * cz(a) * ny) * nx - cx(a) + (cx(a) == 1 ? nx : -nx);
+                    d[a] = (T)RawBits<S>::template load<0>(ra, (uint32_t)((lane_el + c) * es));
+                } else {
+                    d[a] = wall_value<T>(own(a), p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
+                }
+            }
+        }
+    } else {
+        d[0] = (T)RawBits<S>::template load<0>(ra, (uint32_t)(lane_el * es));
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            int sx = x - cx(a), sy = y - cy(a), sz = z - cz(a);
+            const bool in_lid = ghost_in_lid(g, sx, sy, sz);
+            bool wall = false;
+            if (sx < 0 || sx >= nx) { if (g.px) sx = sx < 0 ? sx + nx : sx - nx; else wall = true; }
+            if (sy < 0 || sy >= ny) { if (g.py) sy = sy < 0 ? sy + ny : sy - ny; else wall = true; }
+            if (sz < 0 || sz >= g.nz) { if (g.pz) sz = sz < 0 ? sz + g.nz : sz - g.nz; else wall = true; }
+            if (!wall)
+                d[a] = (T)RawBits<S>::template load<0>(ra, (uint32_t)(((Q * (sy + ny * sz) + a) * nx + sx) * es));
+            else
+                d[a] = wall_value<T>(own(a), p, a, in_lid);
+        }
+    }
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, l + (uint32_t)g.nxy * (uint32_t)z, step);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) RawBits<S>::template store<StAux>(rb, (uint32_t)((lane_el + a * nx) * es), d[a]);
+}
+
+template <typename S, typename T, int Route, int StAux>
+__global__ void __launch_bounds__(MaxThreads<T>::value)
+batch_packed_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
+                    const int32_t *__restrict__ tile_inst, uint32_t ntiles, uint32_t passes,
+                    const uint32_t *__restrict__ step_base, uint32_t step_off) {
+    const uint32_t step = __builtin_amdgcn_readfirstlane(*step_base + step_off);
+    const uint32_t waves = blockDim.x >> 6;
+    const uint32_t w0 = blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t t = w0; t < ntiles; t += gridDim.x * waves) {
+        const int i = __builtin_amdgcn_readfirstlane(tile_inst[t]);
+        const Geom g = inst[i].g;
+        const int64_t base = inst[i].base;
+        const uint32_t local = t - inst[i].tile0;
+        const uint32_t chunks = inst[i].chunks;
+        const int z = (int)(local / chunks);
+        const uint32_t l0 = (local - (uint32_t)z * chunks) * passes * 64u;
+        const Relax<T> &p = inst[i].p;
+        const uint32_t bytes = inst[i].bytes;
+        const float inv_nx = inst[i].inv_nx;
+        for (uint32_t j = 0; j < passes; ++j) {
+            const uint32_t l = l0 + j * 64u;
+            if (l >= (uint32_t)g.nxy) break;
+            if (inst[i].forced)
+                packed_pass<S, T, true, Route, StAux>(A + base, B + base, g, p, bytes, inv_nx, l + lane, z, step);
+            else
+                packed_pass<S, T, false, Route, StAux>(A + base, B + base, g, p, bytes, inv_nx, l + lane, z, step);
+        }
     }
 }
 
 template <typename S, typename T, int StAux>
 static hipError_t launch_batch_h(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
-                                 int route, bool rows, dim3 grid, dim3 block, hipStream_t st) {
+                                 int route, bool rows, uint32_t passes, dim3 grid, dim3 block, BatchStep s,
+                                 hipStream_t st) {
     const S *a = (const S *)A;
     S *b = (S *)B;
     const BatchInst<T> *d = (const BatchInst<T> *)inst;
+    if (rows && passes > 0) {
+        if (route == 0)
+            hipLaunchKernelGGL((batch_packed_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles,
+                               passes, s.base, s.off);
+        else
+            hipLaunchKernelGGL((batch_packed_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles,
+                               passes, s.base, s.off);
+        return hipGetLastError();
+    }
     if (rows) {
         if (route == 0)
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+                               s.off);
         else
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+                               s.off);
         return hipGetLastError();
     }
     if (route == 0)
-        hipLaunchKernelGGL((batch_step_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+                           s.off);
     else
-        hipLaunchKernelGGL((batch_step_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles);
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+                           s.off);
     return hipGetLastError();
 }
 
 template <typename S, typename T>
 static hipError_t launch_batch_t(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
-                                 int route, bool rows, bool nt, dim3 grid, dim3 block, hipStream_t st) {
-    return nt ? launch_batch_h<S, T, 2>(A, B, inst, tiles, ntiles, route, rows, grid, block, st)
-              : launch_batch_h<S, T, 0>(A, B, inst, tiles, ntiles, route, rows, grid, block, st);
+                                 int route, bool rows, uint32_t passes, bool nt, dim3 grid, dim3 block, BatchStep s,
+                                 hipStream_t st) {
+    return nt ? launch_batch_h<S, T, 2>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st)
+              : launch_batch_h<S, T, 0>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st);
 }
 
 static hipError_t launch_batch(int storage, const void *A, void *B, const void *inst, const int32_t *tiles,
-                               uint32_t ntiles, int route, bool rows, bool nt, dim3 grid, dim3 block,
-                               hipStream_t st) {
+                               uint32_t ntiles, int route, bool rows, uint32_t passes, bool nt, dim3 grid, dim3 block,
+                               BatchStep s, hipStream_t st) {
     switch (storage) {
-    case 0: return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, nt, grid, block, st);
-    case 1: return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, nt, grid, block, st);
-    default: return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, nt, grid, block, st);
+    case 0:
+        return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, passes, nt, grid, block, s, st);
+    case 1:
+        return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, passes, nt, grid, block, s, st);
+    default:
+        return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, passes, nt, grid, block, s, st);
     }
+}
+
+__global__ void __launch_bounds__(64) set_step_kernel(uint32_t *__restrict__ p, uint32_t v) {
+    if (threadIdx.x == 0) *p = v;
 }
 
 static uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
@@ -160,6 +301,7 @@ struct clbm_batch {
     clbm_batch_config cfg;
     int num_cus;
     // device tables
+    uint32_t *d_step;       // collision index before the current run of launches
     void *d_inst;
     int32_t *d_tiles;
     size_t tile_cap;
@@ -203,6 +345,8 @@ clbm_status check_config(const clbm_batch *b, const clbm_batch_config *c) {
     if (c->blocks_per_cu < 1 || c->blocks_per_cu > 64) return fail(CLBM_EINVAL, "blocks_per_cu must lie in 1..64");
     if (c->graph_steps < 0 || c->graph_steps > 4096) return fail(CLBM_EINVAL, "graph_steps must lie in 0..4096");
     if (c->nt_stores != 0 && c->nt_stores != 1) return fail(CLBM_EINVAL, "nt_stores must be 0 or 1");
+    if (c->passes < 0 || c->passes > 256) return fail(CLBM_EINVAL, "passes must lie in 0..256");
+    if (c->passes > 0 && !b->rows) return fail(CLBM_EINVAL, "packed items (passes > 0) need the row layout");
     return CLBM_OK;
 }
 
@@ -222,7 +366,12 @@ clbm_status upload_tables_t(clbm_batch *b, const std::vector<Relax<T>> &relax) {
         d.inv_nx = 1.0f / (float)g.nx;
         d.tile0 = (uint32_t)total;
         d.forced = b->forced[i];
-        if (b->rows) {
+        d.bytes = (uint32_t)state_bytes_of(&b->prm[i]);
+        if (b->rows && b->cfg.passes > 0) {
+            const uint64_t per = 64ull * (uint64_t)b->cfg.passes;
+            d.chunks = (uint32_t)(((uint64_t)g.nxy + per - 1) / per);
+            total += (uint64_t)d.chunks * (uint64_t)g.nz;
+        } else if (b->rows) {
             d.chunks = (uint32_t)((g.nx + 63) / 64);
             total += (uint64_t)d.chunks * (uint64_t)g.ny * (uint64_t)g.nz;
         } else {
@@ -233,7 +382,8 @@ clbm_status upload_tables_t(clbm_batch *b, const std::vector<Relax<T>> &relax) {
     if (total > 0x7fffffffull) return fail(CLBM_EINVAL, "batch has more than 2^31 tiles");
     tiles.resize(total);
     for (int i = 0; i < b->count; ++i) {
-        const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz * (b->rows ? (uint64_t)b->geom[i].ny : 1u);
+        const bool per_row = b->rows && b->cfg.passes == 0;
+        const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz * (per_row ? (uint64_t)b->geom[i].ny : 1u);
         std::fill(tiles.begin() + inst[i].tile0, tiles.begin() + inst[i].tile0 + n, i);
     }
     if (total > b->tile_cap) {
@@ -254,13 +404,21 @@ clbm_status upload_tables(clbm_batch *b) {
     return b->storage == CLBM_F64 ? upload_tables_t<double>(b, b->rd) : upload_tables_t<float>(b, b->rf);
 }
 
-hipError_t launch_one_step(clbm_batch *b, int from, hipStream_t st) {
+// Sets the device step base to the steps taken so far (before a run of
+// launches; a kernel, not a copy, so it can precede graph replays).
+hipError_t set_step_base(clbm_batch *b, hipStream_t st) {
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, b->d_step, (uint32_t)b->steps_done);
+    return hipGetLastError();
+}
+
+hipError_t launch_one_step(clbm_batch *b, int from, uint32_t off, hipStream_t st) {
     // rows: a tile is one wave's item, bx / 64 of them per workgroup
     const uint64_t per_block = b->rows ? (uint64_t)(b->cfg.bx / 64) : 1u;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)b->cfg.blocks_per_cu * b->num_cus,
                                                        std::max<uint64_t>((b->ntiles + per_block - 1) / per_block, 1u));
     return launch_batch(b->storage, b->pool[from], b->pool[1 - from], b->d_inst, b->d_tiles, b->ntiles, b->route,
-                        b->rows, b->cfg.nt_stores != 0, dim3(grid), dim3(b->cfg.bx), st);
+                        b->rows, (uint32_t)b->cfg.passes, b->cfg.nt_stores != 0, dim3(grid), dim3(b->cfg.bx),
+                        BatchStep{b->d_step, off}, st);
 }
 
 clbm_status build_graph(clbm_batch *b, int parity) {
@@ -269,7 +427,7 @@ clbm_status build_graph(clbm_batch *b, int parity) {
     int c = parity;
     hipError_t e = hipSuccess;
     for (int s = 0; s < k && e == hipSuccess; ++s) {
-        e = launch_one_step(b, c, b->cap_stream);
+        e = launch_one_step(b, c, (uint32_t)s + 1u, b->cap_stream);
         c = 1 - c;
     }
     hipGraph_t graph = nullptr;
@@ -313,8 +471,8 @@ bool read_cache(clbm_batch *b, clbm_batch_config *out) {
     char key[256];
     clbm_batch_config c;
     bool found = false;
-    while (fscanf(fh, "%255s %d %d %d %d %d", key, &c.bx, &c.by, &c.blocks_per_cu, &c.graph_steps, &c.nt_stores) ==
-           6) {
+    while (fscanf(fh, "%255s %d %d %d %d %d %d", key, &c.bx, &c.by, &c.blocks_per_cu, &c.graph_steps, &c.nt_stores,
+                  &c.passes) == 7) {
         if (b->cache_key == key && check_config(b, &c) == CLBM_OK) {
             *out = c;
             found = true;       // the last entry for a key wins
@@ -328,8 +486,8 @@ void append_cache(clbm_batch *b, const clbm_batch_config &c, double ms) {
     if (b->cache_path.empty()) return;
     FILE *fh = fopen(b->cache_path.c_str(), "a");
     if (!fh) return;
-    fprintf(fh, "%s %d %d %d %d %d\n", b->cache_key.c_str(), c.bx, c.by, c.blocks_per_cu, c.graph_steps,
-            c.nt_stores);
+    fprintf(fh, "%s %d %d %d %d %d %d\n", b->cache_key.c_str(), c.bx, c.by, c.blocks_per_cu, c.graph_steps,
+            c.nt_stores, c.passes);
     (void)ms;
     fclose(fh);
 }
@@ -362,6 +520,9 @@ clbm_status clbm_batch_size(const clbm_params *inst, int32_t count, size_t *byte
         // one correction, exact while a layer has at most 2^22 nodes
         if ((int64_t)inst[i].nx * inst[i].ny > ((int64_t)1 << 22))
             return fail(CLBM_EINVAL, "instance %d: a z layer of more than 2^22 nodes", i);
+        // row layout: packed items address an instance's state with 32-bit signed byte offsets
+        if (inst[i].layout == CLBM_LAYOUT_ROWS && state_bytes_of(&inst[i]) >= ((size_t)1 << 31) - ((size_t)1 << 24))
+            return fail(CLBM_EINVAL, "instance %d: a state of 2 GiB or more in a row-layout batch", i);
         total += instance_bytes(&inst[i]);
     }
     if (bytes_each) *bytes_each = total;
@@ -407,6 +568,7 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
     b->cfg.blocks_per_cu = 8;
     b->cfg.graph_steps = 20;
     b->cfg.nt_stores = 0;
+    b->cfg.passes = b->rows ? 4 : 0;
     b->num_cus = 256;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -419,6 +581,8 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
 
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     const size_t inst_size = b->storage == CLBM_F64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_step, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(b->d_step, 0, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&b->d_inst, inst_size * count);
     int64_t maxn = 0;
     for (int i = 0; i < count; ++i) maxn = std::max<int64_t>(maxn, (int64_t)b->geom[i].n);
@@ -448,6 +612,7 @@ clbm_status clbm_batch_destroy(clbm_batch *b) {
     if (!b) return CLBM_OK;
     drop_graphs(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_step) (void)hipFree(b->d_step);
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->partials) (void)hipFree(b->partials);
@@ -515,13 +680,15 @@ clbm_status clbm_batch_step(clbm_batch *b, int64_t nsteps, void *stream) {
             clbm_status s = build_graph(b, b->cur);
             if (s != CLBM_OK) return s;
         }
+        HIP_TRY(set_step_base(b, st), "clbm_batch_step: step base");
         HIP_TRY(hipGraphLaunch(b->exec[b->cur], st), "clbm_batch_step: graph launch");
         if (k & 1) b->cur = 1 - b->cur;
         b->steps_done += k;
         nsteps -= k;
     }
-    for (; nsteps > 0; --nsteps) {
-        HIP_TRY(launch_one_step(b, b->cur, st), "clbm_batch_step");
+    if (nsteps > 0) HIP_TRY(set_step_base(b, st), "clbm_batch_step: step base");
+    for (uint32_t off = 1; nsteps > 0; --nsteps, ++off) {
+        HIP_TRY(launch_one_step(b, b->cur, off, st), "clbm_batch_step");
         b->cur = 1 - b->cur;
         b->steps_done++;
     }
@@ -547,14 +714,17 @@ clbm_status clbm_batch_step_each(clbm_batch *b, int64_t nsteps, void *stream) {
             c.fuse_steps = 1;
             c.fuse_rows = 8;
             c.fuse_planes = 1;
+            Relax<double> pd = b->rd[i];
+            Relax<float> pf = b->rf[i];
+            pd.step = pf.step = (uint32_t)(b->steps_done + 1);
             if (b->rows) {
                 if (nx >= 64) c.by = 1;         // one lattice row per block, as for a single lattice
                 HIP_TRY(launch_step_rows(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
-                                         b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
+                                         b->geom[i], pd, pf, b->forced[i], b->route, c, st),
                         "clbm_batch_step_each");
             } else {
                 HIP_TRY(launch_step(b->storage, storage_ptr(b, b->cur, i), (void *)storage_ptr(b, 1 - b->cur, i),
-                                    b->geom[i], b->rd[i], b->rf[i], b->forced[i], b->route, c, st),
+                                    b->geom[i], pd, pf, b->forced[i], b->route, c, st),
                         "clbm_batch_step_each");
             }
         }
@@ -626,7 +796,7 @@ clbm_status clbm_batch_set_config(clbm_batch *b, const clbm_batch_config *c) {
     if (!b || !c) return fail(CLBM_EINVAL, "NULL argument");
     clbm_status st = check_config(b, c);
     if (st != CLBM_OK) return st;
-    const bool tiles_change = c->bx != b->cfg.bx || c->by != b->cfg.by;
+    const bool tiles_change = c->bx != b->cfg.bx || c->by != b->cfg.by || c->passes != b->cfg.passes;
     b->cfg = *c;
     drop_graphs(b);
     return tiles_change ? upload_tables(b) : CLBM_OK;
@@ -658,19 +828,22 @@ clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *
     HIP_TRY(hipEventCreate(&e0), "autotune: event");
     HIP_TRY(hipEventCreate(&e1), "autotune: event");
     clbm_status result = CLBM_OK;
-    for (const auto &sh : shapes) {
+    static const int packings[] = {0, 2, 4, 8};     // row layout: one row run per item, or packed passes
+    for (const auto &sh : shapes)
+    for (int pk : packings) {
         clbm_batch_config c = keep;
         c.bx = sh[0];
         c.by = sh[1];
+        c.passes = pk;
         if (check_config(b, &c) != CLBM_OK) continue;
         for (int k = 0; k < 8; ++k) {
             c.blocks_per_cu = bpcs[k % 4];
             c.nt_stores = k / 4;
             if ((result = clbm_batch_set_config(b, &c)) != CLBM_OK) break;
             // trials read the state and write the spare pool: the state is unchanged
-            hipError_t e = launch_one_step(b, b->cur, st);
+            hipError_t e = launch_one_step(b, b->cur, 1u, st);
             if (e == hipSuccess) e = hipEventRecord(e0, st);
-            for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_one_step(b, b->cur, st);
+            for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_one_step(b, b->cur, 1u, st);
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;

@@ -197,7 +197,40 @@ template <typename T> struct Relax {
     T force[3];
     int32_t newtonian;      // n == 1
     int32_t literal;        // fourth-order attractor without 1/rho
+    int32_t sr;             // FP16 storage: stochastic rounding of the stored values (else nearest even)
+    uint32_t step;          // index of the collision a launch performs (0: the initial one); keys the rounding
 };
+
+// ---------------------------------------------------------------------------
+// Stochastic rounding of the FP16 state
+// ---------------------------------------------------------------------------
+// Round-to-nearest of slowly varying FP16 values repeats the same rounding
+// error step after step, which acts on the flow like a spurious source term.
+// Rounding each stored value up or down at random, with the probability that
+// makes the expected result equal to the FP32 value, turns that bias into
+// zero-mean noise.  The random bits come from a counter-based hash of
+// (node, step) — a bijective integer mixer (xor-shift / odd-multiply rounds)
+// — offset per direction by a Weyl increment, so every launch form and
+// layout draws the same bits for the same value and results do not depend on
+// the launch configuration.  gfx950 converts with a seed in hardware.
+__host__ __device__ constexpr uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+constexpr uint32_t kWeyl = 0x9E3779B9u;    // 2^32 / golden ratio
+
+// key of a collision index, uniform over a launch
+__host__ __device__ constexpr uint32_t step_key(uint32_t step) { return mix32(step * 0x85EBCA77u + 0x27D4EB2Fu); }
+
+__device__ inline float sr_to_f16_grid(float v, uint32_t seed) {
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(half2_t{0, 0}, v, seed, false);
+    return (float)h[0];
+}
 
 // ---------------------------------------------------------------------------
 // Local relaxation rate omega^nu (Sec. 3.2)

@@ -167,6 +167,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
                 gather<S, T, 0>(Am, g, p, wx, wy, wz, self, d);
             }
             collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+            round_state<S, T>(d, p, self, p.step);
         } else {
 #pragma unroll
             for (int a = 0; a < Q; ++a) d[a] = T(0);
@@ -231,6 +232,7 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
             }
         }
         collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+        round_state<S, T>(d, p, (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy + (uint32_t)g.nxy * (uint32_t)z, p.step + 1u);
         if constexpr (Rows) {
             row_store<S, T, StAux>(B, g, gx, gy, z, d);
         } else {

@@ -86,7 +86,8 @@ inline clbm_status validate(const clbm_params *p) {
         return fail(CLBM_EINVAL, "unknown storage %d", p->storage);
     if (p->layout != CLBM_LAYOUT_PLANES && p->layout != CLBM_LAYOUT_ROWS)
         return fail(CLBM_EINVAL, "unknown layout %d", p->layout);
-    if (p->reserved != 0) return fail(CLBM_EINVAL, "reserved field must be 0");
+    if (p->f16_rounding != CLBM_F16_STOCHASTIC && p->f16_rounding != CLBM_F16_NEAREST_EVEN)
+        return fail(CLBM_EINVAL, "unknown f16_rounding %d", p->f16_rounding);
     // one population plane is addressed through a buffer descriptor with a
     // 32-bit byte range; node indices are 32-bit in either layout
     if (p->layout == CLBM_LAYOUT_PLANES && N * (int64_t)elem_bytes(p->storage) > ((int64_t)1 << 32) - 256)
@@ -145,6 +146,8 @@ inline Relax<T> make_relax(const clbm_params *p) {
     for (int d = 0; d < 3; ++d) r.force[d] = (T)p->force[d];
     r.newtonian = p->n == 1.0;
     r.literal = p->attractor_literal;
+    r.sr = p->storage == CLBM_F16_DEV && p->f16_rounding == CLBM_F16_STOCHASTIC;
+    r.step = 0;
     return r;
 }
 

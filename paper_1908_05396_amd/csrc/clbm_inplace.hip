@@ -56,6 +56,7 @@ aa_even_kernel(S *__restrict__ A, Geom g, Relax<T> p, LaunchGrid L) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = (T)Plane<S>::load(A, g, a, self);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, self, p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) Plane<S, EvenStAux>::store(A, g, opp(a), self, d[a]);
 }
@@ -88,6 +89,7 @@ aa_odd_kernel(S *__restrict__ A, Geom g, Relax<T> p, LaunchGrid L) {
         }
     }
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, self, p.step);
     if (!edge) {
 #pragma unroll
         for (int a = 0; a < Q; ++a)
@@ -141,6 +143,7 @@ aa_even_rows_kernel(S *__restrict__ A, Geom g, Relax<T> p, RowGrid R) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = (T)RawBits<S>::template load<0>(own, lane, (uint32_t)a * run);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * ri, p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) RawBits<S>::template store<EvenStAux>(own, lane, d[a], (uint32_t)opp(a) * run);
 }
@@ -190,6 +193,7 @@ __device__ inline void aa_odd_row(S *__restrict__ A, const Geom &g, const Relax<
                                      (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
     }
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * (uint32_t)r, p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         if (xwall && ((xl && cx(a) == -1) || (xr && cx(a) == 1))) continue;
@@ -215,6 +219,7 @@ __device__ inline void aa_even_any(S *__restrict__ A, const Geom &g, const Relax
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = (T)Conv<S, T>::load(A[elem(g, a, x, y, z)]);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z), p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) A[elem(g, opp(a), x, y, z)] = Conv<S, T>::store(d[a]);
 }
@@ -231,6 +236,7 @@ __device__ inline void aa_odd_any(S *__restrict__ A, const Geom &g, const Relax<
                   : wall_value<T>((T)Conv<S, T>::load(A[elem(g, a, x, y, z)]), p, a, in_lid);
     }
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z), p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         int tx = x + cx(a), ty = y + cy(a), tz = z + cz(a);
@@ -286,17 +292,19 @@ static hipError_t aa_pair_rows_f(void *A, const Geom &g, const Relax<T> &p, cons
     all.rows = (uint32_t)g.ny * (uint32_t)g.nz;
     const uint32_t nb = all.gx * ((all.rows + c.by - 1) / c.by);
     all.aligned = nb & ~7u;
+    Relax<T> q = p;             // the odd step is the next collision
+    q.step = p.step + 1u;
     hipLaunchKernelGGL((aa_even_rows_kernel<S, T, Forced, Route>), dim3(nb), block, 0, st, (S *)A, g, p, all);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (L.inner.rows > 0) {
         hipLaunchKernelGGL((aa_odd_rows_kernel<S, T, Forced, Route>), dim3(L.inner_blocks), block, 0, st, (S *)A, g,
-                           p, L.inner);
+                           q, L.inner);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((aa_odd_rows_face_kernel<S, T, Forced, Route>), dim3(L.face_blocks), block, 0, st, (S *)A, g,
-                       p, L.face);
+                       q, L.face);
     return hipGetLastError();
 }
 
@@ -311,17 +319,19 @@ static hipError_t aa_pair_f(void *A, const Geom &g, const Relax<T> &p, const Ste
     L.aligned = nb & ~7u;
     L.remap = c.xcd_remap;
     dim3 grid(nb), block(c.bx, c.by);
+    Relax<T> q = p;             // the odd step is the next collision
+    q.step = p.step + 1u;
     if (g.rows) {
         hipLaunchKernelGGL((aa_any_kernel<S, T, Forced, Route, false>), grid, block, 0, st, (S *)A, g, p, L);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((aa_any_kernel<S, T, Forced, Route, true>), grid, block, 0, st, (S *)A, g, p, L);
+        hipLaunchKernelGGL((aa_any_kernel<S, T, Forced, Route, true>), grid, block, 0, st, (S *)A, g, q, L);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((aa_even_kernel<S, T, Forced, Route>), grid, block, 0, st, (S *)A, g, p, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((aa_odd_kernel<S, T, Forced, Route>), grid, block, 0, st, (S *)A, g, p, L);
+    hipLaunchKernelGGL((aa_odd_kernel<S, T, Forced, Route>), grid, block, 0, st, (S *)A, g, q, L);
     return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // Internal declarations shared by the kernel and runtime translation units.
 #pragma once
 
+#include <type_traits>
+
 #include "clbm_device.hpp"
 
 namespace clbm {
@@ -66,6 +68,21 @@ __device__ inline void collide(T d[Q], const Relax<T> &p, T *omega_out) {
     }
 }
 
+// FP16 storage with stochastic rounding: replace the post-collision values of
+// node `node` by FP16 values drawn up or down (exactly representable, so the
+// stores that follow convert them without further rounding).  No-op for the
+// other storage types and for round-to-nearest.
+template <typename S, typename T>
+__device__ inline void round_state(T d[Q], const Relax<T> &p, uint32_t node, uint32_t step) {
+    if constexpr (std::is_same<S, __half>::value) {
+        if (p.sr) {
+            const uint32_t base = mix32(node ^ step_key(step));
+#pragma unroll
+            for (int a = 0; a < Q; ++a) d[a] = sr_to_f16_grid(d[a], base + (uint32_t)a * kWeyl);
+        }
+    }
+}
+
 // Newton steps of the FP32 relaxation-rate solve per storage type: four reach
 // FP32 precision (relative tau error <= 4e-13 in exact arithmetic over n in
 // [0.4, 1.6], K over five decades, a over twelve); FP16 storage, whose
@@ -75,6 +92,8 @@ template <> struct NewtonSteps<__half> { static constexpr int value = 3; };
 hipError_t launch_macroscopic(int storage, const void *A, const uint8_t *flags, void *rho, void *u, bool out_f32,
                               const Geom &g, const double *F, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_f16_round(const float *in, const uint32_t *seeds, uint16_t *out, int64_t n, int stochastic,
+                            hipStream_t st);
 hipError_t launch_export(int storage, const void *A, double *f, const Geom &g, hipStream_t st);
 hipError_t launch_reduce(int storage, const void *A, const uint8_t *flags, double *snap, int have_prev,
                          const Geom &g, const double *F, double *partials, int nblocks, double *out, hipStream_t st);

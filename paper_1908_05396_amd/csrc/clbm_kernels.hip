@@ -43,11 +43,13 @@ stream_collide_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax<
     if constexpr (G == 1) {
         gather<S, T, LdAux>(A, g, p, x, y, z, self, d);
         collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+        round_state<S, T>(d, p, self, p.step);
 #pragma unroll
         for (int a = 0; a < Q; ++a) Plane<S, StAux>::store(B, g, a, self, d[a]);
     } else {
         gather_grouped<S, T, LdAux, G>(A, g, p, x, y, z, self, d);
         collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+        round_state<S, T>(d, p, self, p.step);
         const uint32_t sb = self * (uint32_t)sizeof(S);
 #pragma unroll
         for (int a = 0; a < Q; ++a)
@@ -99,6 +101,7 @@ stream_collide_flags_kernel(const S *__restrict__ A, S *__restrict__ B, const ui
         for (int a = 0; a < Q; ++a)
             d[a] = a == 0 ? (T)Conv<S, T>::load(A[elem(g, 0, x, y, z)]) : pull_flagged<S, T>(A, flags, g, p, a, x, y, z);
         collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+        round_state<S, T>(d, p, (uint32_t)i, p.step);
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a) B[elem(g, a, x, y, z)] = Conv<S, T>::store(d[a]);
@@ -136,6 +139,7 @@ init_collide_kernel(const double *__restrict__ f0, S *__restrict__ B, const uint
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = f0 ? (T)(f0[(int64_t)a * N + i] - weight(a)) : T(0);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)i, p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) B[elem_i(g, a, i)] = Conv<S, T>::store(d[a]);
 }
@@ -365,6 +369,29 @@ hipError_t launch_reduce_noalloc(int storage, const void *A, const uint8_t *flag
     case 1: return launch_reduce_noalloc_t<float>(A, flags, snap, have_prev, g, F, nblocks, out, st);
     default: return launch_reduce_noalloc_t<__half>(A, flags, snap, have_prev, g, F, nblocks, out, st);
     }
+}
+
+// ---------------------------------------------------------------------------
+// The FP16 rounding of the state on its own (test utility): stochastic with
+// the given seeds (the hardware conversion the step kernels use), or nearest
+// even.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+f16_round_kernel(const float *__restrict__ in, const uint32_t *__restrict__ seeds, uint16_t *__restrict__ out,
+                 int64_t n, int stochastic) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = stochastic ? sr_to_f16_grid(in[i], seeds[i]) : in[i];
+    out[i] = __builtin_bit_cast(uint16_t, __float2half_rn(v));
+}
+
+hipError_t launch_f16_round(const float *in, const uint32_t *seeds, uint16_t *out, int64_t n, int stochastic,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f16_round_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, seeds, out, n, stochastic);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -62,7 +62,7 @@ stream_collide_rows_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, R
     if (!row_of(R, x, ri) || x >= g.nx) return;
     int y, z;
     inner_row(g, ri, y, z);
-    row_step<S, T, Forced, LdAux, StAux, Route, false>(A, B, g, p, x, y, z);
+    row_step<S, T, Forced, LdAux, StAux, Route, false>(A, B, g, p, x, y, z, p.step);
 }
 
 template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
@@ -73,7 +73,7 @@ stream_collide_rows_face_kernel(const S *__restrict__ A, S *__restrict__ B, Geom
     if (!row_of(R, x, ri) || x >= g.nx) return;
     int y, z;
     face_row(g, R, ri, y, z);
-    row_step<S, T, Forced, LdAux, StAux, Route, true>(A, B, g, p, x, y, z);
+    row_step<S, T, Forced, LdAux, StAux, Route, true>(A, B, g, p, x, y, z, p.step);
 }
 
 template <typename S, typename T, bool Forced, int Route>
@@ -89,6 +89,7 @@ stream_collide_any_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Re
 #pragma unroll
     for (int a = 0; a < Q; ++a) d[a] = pull_any<S, T>(A, g, p, a, x, y, z);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z), p.step);
 #pragma unroll
     for (int a = 0; a < Q; ++a) B[elem(g, a, x, y, z)] = Conv<S, T>::store(d[a]);
 }

@@ -163,13 +163,15 @@ __device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y,
         RawBits<S>::template store<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a]);
 }
 
-// One step of node x of row (y, z): gather, collide, store.
+// One step of node x of row (y, z): gather, collide, store; `step` is the
+// index of the collision (keys the stochastic rounding of FP16 storage).
 template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face>
 __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p, int x,
-                                int y, int z) {
+                                int y, int z, uint32_t step) {
     T d[Q];
     row_gather<S, T, LdAux, Face>(A, g, p, x, y, z, d);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z), step);
     row_store<S, T, StAux>(B, g, x, y, z, d);
 }
 

@@ -158,7 +158,7 @@ def test_params_struct_layout(clbm):
     assert clbm.load().clbm_params_default(ctypes.byref(p)) == 0
     assert (p.nx, p.ny, p.nz) == (1, 1, 1)
     assert p.storage == 1 and p.omega_bulk == 1.0 and p.rho_wall == 1.0
-    assert p.layout == clbm.LAYOUT["rows"] and p.reserved == 0
+    assert p.layout == clbm.LAYOUT["rows"] and p.f16_rounding == clbm.F16_ROUNDING["stochastic"]
     assert list(p.omega_high) == [1.0] * 9
 
 
@@ -182,7 +182,7 @@ def test_buffer_size_padding(clbm, storage, esize):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("K", 0.0), ("K", float("nan")), ("n", -1.0), ("nu_min", 0.0), ("nu_max", 1e-6),
     ("omega_bulk", 2.0), ("rho_wall", 0.0), ("storage", 7), ("lid_face", 9), ("attractor_literal", 2),
-    ("collision", 4), ("plane_pad", -2), ("layout", 2), ("layout", -1), ("reserved", 1),
+    ("collision", 4), ("plane_pad", -2), ("layout", 2), ("layout", -1), ("f16_rounding", 2),
 ])
 def test_invalid_parameters_rejected(clbm, field, value):
     p = clbm.params_from_spec(W.cavity(8, 0.05, 1.0, 10.0), "f32")

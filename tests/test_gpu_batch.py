@@ -41,15 +41,17 @@ def _mixed_specs():
 EPS = [1e-3, 1e-3, 1e-3, 1e-3, 5e-2, 1e-3, 1e-3]
 
 
-@pytest.mark.parametrize("layout", ["rows", "planes"])
-def test_batch_matches_oracle_per_instance(clbm, layout):
+@pytest.mark.parametrize("layout,passes", [("rows", 0), ("rows", 1), ("rows", 3), ("planes", 0)])
+def test_batch_matches_oracle_per_instance(clbm, layout, passes):
+    """Row layout: items of one row run (passes = 0) or packed passes of 64
+    consecutive nodes of a z layer (1 and 3 passes per item)."""
     specs = _mixed_specs()
     steps = 70
     b = clbm.Batch(specs, storage="f64", layout=layout)
     b.init_rest()
     for i, sp in enumerate(specs):
         b.init_populations(i, W.perturbed_populations(sp, 40 + i, EPS[i], device="cuda"))
-    b.set_config(graph_steps=20)
+    b.set_config(graph_steps=20, passes=passes)
     b.step(steps)          # three graph replays and ten plain launches
     torch.cuda.synchronize()
     for i, sp in enumerate(specs):
@@ -103,6 +105,29 @@ def test_graph_replay_equals_plain_launches(clbm, layout):
     for other in outs[1:]:
         for x, y in zip(outs[0], other):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_packings_agree(clbm, storage):
+    """Row layout: one row run per item and packed items of 1, 2 and 5
+    passes give the same state to rounding (the kernels may contract
+    multiply-adds differently; FP16 stores the same stochastic rounding)."""
+    specs = _mixed_specs()
+    outs = []
+    for passes in (0, 1, 2, 5):
+        b = clbm.Batch(specs, storage=storage, layout="rows")
+        b.set_config(passes=passes)
+        b.init_rest()
+        for i, sp in enumerate(specs):
+            b.init_populations(i, W.perturbed_populations(sp, 17 + i, 1e-3, device="cuda"))
+        b.step(21)
+        outs.append([b.populations(i).cpu().numpy() for i in range(len(specs))])
+        b.close()
+    for other in outs[1:]:
+        for x, y in zip(outs[0], other):
+            assert np.abs(x - y).max() < ATOL[storage]
+    with pytest.raises(clbm.ClbmError):
+        clbm.Batch(specs, storage="f32", layout="planes").set_config(passes=2)
 
 
 @pytest.mark.parametrize("layout", ["rows", "planes"])

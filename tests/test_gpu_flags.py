@@ -82,9 +82,10 @@ def test_flagged_cavity_matches_oracle_and_box(clbm, storage, layout):
     print(f"flagged cavity {storage} {layout}: {err:.3e}")
     assert err < TOL_U[storage]
     assert np.all(u[:, fl != 0] == 0.0) and np.all(rho[fl != 0] == 1.0)
-    # reductions over the fluid nodes only: mass of the 210 fluid nodes
+    # reductions over the fluid nodes only: mass of the 210 fluid nodes (FP32:
+    # the rounding of the stored deviations, ~1e-10 per node after 60 steps)
     fluid = fl == 0
-    assert abs(r["mass"] - rho_ref[fluid].sum()) < 1e-11 * fluid.sum()
+    assert abs(r["mass"] - rho_ref[fluid].sum()) < {"f64": 1e-11, "f32": 1e-9}[storage] * fluid.sum()
     # the box run through the tuned (unflagged) kernels
     lat = clbm.Lattice(box, storage=storage, layout=layout)
     lat.init_populations(torch.from_numpy(f0).to("cuda"))
@@ -108,7 +109,7 @@ def test_flagged_obstacle_channel(clbm, storage, layout):
     print(f"obstacle channel {storage} {layout}: {err:.3e}")
     assert err < TOL_U[storage]
     fluid = fl == 0
-    assert abs(r["mass"] - rho_ref[fluid].sum()) < 1e-10 * fluid.sum()
+    assert abs(r["mass"] - rho_ref[fluid].sum()) < {"f64": 1e-11, "f32": 1e-9}[storage] * fluid.sum()
     mom = (rho_ref[None] * u_ref)[:, fluid].sum(axis=1)
     assert abs(r["momentum_x"] - mom[0]) < (1e-12 if storage == "f64" else 1e-5) * abs(mom[0])
 
