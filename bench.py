@@ -470,6 +470,8 @@ def main():
                     help="skip the other launch form, the planes layout, the BGK comparison and the one-buffer "
                          "form (short runs under a profiler)")
     ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 64-cavity batch (its own JSON line; for profiling the batch kernel)")
     ap.add_argument("--stability", action="store_true",
                     help="instead of the benchmark: largest stable lid velocity of the 64^3 cavity, cascaded "
                          "scheme vs the single-relaxation-time comparison model")
@@ -510,6 +512,9 @@ def main():
         return
     if args.accuracy64:
         print(json.dumps(accuracy64(clbm, torch, W, args.accuracy64)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batched(clbm, torch, W, "f32", args.batch_steps, args.spinup)), flush=True)
         return
     if args.accuracy512:
         print(json.dumps(accuracy_run(clbm, torch, W.config_cavity512(), args.accuracy512, 1000)[0]), flush=True)

@@ -107,9 +107,10 @@ typedef enum {
  * the expected stored value equal to the FP32 result, so rounding errors do
  * not repeat from step to step (round-to-nearest of a slowly changing value
  * repeats the same error every step, a bias that accumulates in the flow).
- * The random bits are a counter-based hash of (node, direction, collision
- * index): results are reproducible and do not depend on the launch form,
- * layout or block shape.  Nearest even: IEEE round-to-nearest-even. */
+ * The random bits are a counter-based hash of the node and the collision
+ * index, offset per direction: results are reproducible and do not depend on
+ * the launch form, layout or block shape.  Nearest even: IEEE
+ * round-to-nearest-even. */
 typedef enum { CLBM_F16_STOCHASTIC = 0, CLBM_F16_NEAREST_EVEN = 1 } clbm_f16_rounding;
 
 /* Per-node flag values of the optional flag array of clbm_create: a fluid
@@ -359,9 +360,10 @@ typedef struct {
     int32_t nt_stores;         /* 1: non-temporal (streaming) stores, 0: plain stores (default: the
                                   short runs of small lattices leave partial cache lines, which plain
                                   stores let the cache merge) */
-    int32_t passes;            /* row layout: 0 = each wave item is one row's run of 64 x; k > 0 = each
-                                  item is k passes of 64 consecutive nodes of a z layer (rows packed
-                                  into whole waves; default 4); planes layout: must be 0 */
+    int32_t passes;            /* row layout: 0 = each wave item is one row's run of 64 x (default);
+                                  k > 0 = each item is k passes of 64 consecutive nodes of a z layer
+                                  (rows packed into whole waves: fewer idle lanes for narrow lattices,
+                                  per-lane row addressing); planes layout: must be 0 */
 } clbm_batch_config;
 
 /* Bytes each of the two pools must hold for these instances. */

@@ -36,7 +36,7 @@ template <typename T> struct BatchInst {
 // storage) is *step_base + step_off: step_base is set on the stream before
 // each run of launches, step_off is the launch's place in that run, so that
 // launches captured in a graph draw new rounding bits on every replay.
-template <typename S, typename T, int Route, int StAux>
+template <typename S, typename T, int Route, int StAux, bool AnyForced>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
                   const int32_t *__restrict__ tile_inst, uint32_t ntiles, const uint32_t *__restrict__ step_base,
@@ -60,7 +60,7 @@ batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
         T d[Q];
         gather<S, T, 0>(A + base, g, p, x, y, z, self, d);
-        if (inst[i].forced)
+        if (AnyForced && inst[i].forced)
             collide<T, true, Route, NewtonSteps<S>::value>(d, p, nullptr);
         else
             collide<T, false, Route, NewtonSteps<S>::value>(d, p, nullptr);
@@ -79,7 +79,7 @@ __device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T>
         row_step<S, T, Forced, 0, StAux, Route, false>(A, B, g, p, x, y, z, step);
 }
 
-template <typename S, typename T, int Route, int StAux>
+template <typename S, typename T, int Route, int StAux, bool AnyForced>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
                   const int32_t *__restrict__ tile_inst, uint32_t ntiles, const uint32_t *__restrict__ step_base,
@@ -99,7 +99,7 @@ batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         const int y = (int)(row % (uint32_t)g.ny), z = (int)(row / (uint32_t)g.ny);
         if (x >= g.nx) continue;
         const Relax<T> &p = inst[i].p;
-        if (inst[i].forced)
+        if (AnyForced && inst[i].forced)
             batch_row<S, T, true, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
         else
             batch_row<S, T, false, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
@@ -177,12 +177,21 @@ __device__ inline void packed_pass(const S *__restrict__ A, S *__restrict__ B, c
         }
     }
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
-    round_state<S, T>(d, p, l + (uint32_t)g.nxy * (uint32_t)z, step);
+    if constexpr (std::is_same<S, __half>::value) {
+        if (p.sr) {
+            const uint32_t base = sr_base(l + (uint32_t)g.nxy * (uint32_t)z, step);
+#pragma unroll
+            for (int a = 0; a < Q; ++a)
+                RawBits<S>::template store_sr<StAux>(rb, (uint32_t)((lane_el + a * nx) * es), d[a],
+                                                     base + (uint32_t)a * kWeyl);
+            return;
+        }
+    }
 #pragma unroll
     for (int a = 0; a < Q; ++a) RawBits<S>::template store<StAux>(rb, (uint32_t)((lane_el + a * nx) * es), d[a]);
 }
 
-template <typename S, typename T, int Route, int StAux>
+template <typename S, typename T, int Route, int StAux, bool AnyForced>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_packed_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
                     const int32_t *__restrict__ tile_inst, uint32_t ntiles, uint32_t passes,
@@ -205,7 +214,7 @@ batch_packed_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<
         for (uint32_t j = 0; j < passes; ++j) {
             const uint32_t l = l0 + j * 64u;
             if (l >= (uint32_t)g.nxy) break;
-            if (inst[i].forced)
+            if (AnyForced && inst[i].forced)
                 packed_pass<S, T, true, Route, StAux>(A + base, B + base, g, p, bytes, inv_nx, l + lane, z, step);
             else
                 packed_pass<S, T, false, Route, StAux>(A + base, B + base, g, p, bytes, inv_nx, l + lane, z, step);
@@ -213,7 +222,7 @@ batch_packed_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<
     }
 }
 
-template <typename S, typename T, int StAux>
+template <typename S, typename T, int StAux, bool AF>
 static hipError_t launch_batch_h(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
                                  int route, bool rows, uint32_t passes, dim3 grid, dim3 block, BatchStep s,
                                  hipStream_t st) {
@@ -222,49 +231,56 @@ static hipError_t launch_batch_h(const void *A, void *B, const void *inst, const
     const BatchInst<T> *d = (const BatchInst<T> *)inst;
     if (rows && passes > 0) {
         if (route == 0)
-            hipLaunchKernelGGL((batch_packed_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles,
+            hipLaunchKernelGGL((batch_packed_kernel<S, T, 0, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles,
                                passes, s.base, s.off);
         else
-            hipLaunchKernelGGL((batch_packed_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles,
+            hipLaunchKernelGGL((batch_packed_kernel<S, T, 1, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles,
                                passes, s.base, s.off);
         return hipGetLastError();
     }
     if (rows) {
         if (route == 0)
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
                                s.off);
         else
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
                                s.off);
         return hipGetLastError();
     }
     if (route == 0)
-        hipLaunchKernelGGL((batch_step_kernel<S, T, 0, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 0, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
                            s.off);
     else
-        hipLaunchKernelGGL((batch_step_kernel<S, T, 1, StAux>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
+        hipLaunchKernelGGL((batch_step_kernel<S, T, 1, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
                            s.off);
     return hipGetLastError();
 }
 
 template <typename S, typename T>
 static hipError_t launch_batch_t(const void *A, void *B, const void *inst, const int32_t *tiles, uint32_t ntiles,
-                                 int route, bool rows, uint32_t passes, bool nt, dim3 grid, dim3 block, BatchStep s,
-                                 hipStream_t st) {
-    return nt ? launch_batch_h<S, T, 2>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st)
-              : launch_batch_h<S, T, 0>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st);
+                                 int route, bool rows, uint32_t passes, bool nt, bool any_forced, dim3 grid, dim3 block,
+                                 BatchStep s, hipStream_t st) {
+    // batches without a body force get kernels without the forced collision (half the code)
+    if (any_forced)
+        return nt ? launch_batch_h<S, T, 2, true>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st)
+                  : launch_batch_h<S, T, 0, true>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st);
+    return nt ? launch_batch_h<S, T, 2, false>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st)
+              : launch_batch_h<S, T, 0, false>(A, B, inst, tiles, ntiles, route, rows, passes, grid, block, s, st);
 }
 
 static hipError_t launch_batch(int storage, const void *A, void *B, const void *inst, const int32_t *tiles,
-                               uint32_t ntiles, int route, bool rows, uint32_t passes, bool nt, dim3 grid, dim3 block,
-                               BatchStep s, hipStream_t st) {
+                               uint32_t ntiles, int route, bool rows, uint32_t passes, bool nt, bool any_forced,
+                               dim3 grid, dim3 block, BatchStep s, hipStream_t st) {
     switch (storage) {
     case 0:
-        return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, passes, nt, grid, block, s, st);
+        return launch_batch_t<double, double>(A, B, inst, tiles, ntiles, route, rows, passes, nt, any_forced, grid,
+                                              block, s, st);
     case 1:
-        return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, passes, nt, grid, block, s, st);
+        return launch_batch_t<float, float>(A, B, inst, tiles, ntiles, route, rows, passes, nt, any_forced, grid, block,
+                                            s, st);
     default:
-        return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, passes, nt, grid, block, s, st);
+        return launch_batch_t<__half, float>(A, B, inst, tiles, ntiles, route, rows, passes, nt, any_forced, grid,
+                                             block, s, st);
     }
 }
 
@@ -417,8 +433,9 @@ hipError_t launch_one_step(clbm_batch *b, int from, uint32_t off, hipStream_t st
     const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)b->cfg.blocks_per_cu * b->num_cus,
                                                        std::max<uint64_t>((b->ntiles + per_block - 1) / per_block, 1u));
     return launch_batch(b->storage, b->pool[from], b->pool[1 - from], b->d_inst, b->d_tiles, b->ntiles, b->route,
-                        b->rows, (uint32_t)b->cfg.passes, b->cfg.nt_stores != 0, dim3(grid), dim3(b->cfg.bx),
-                        BatchStep{b->d_step, off}, st);
+                        b->rows, (uint32_t)b->cfg.passes, b->cfg.nt_stores != 0,
+                        std::any_of(b->forced.begin(), b->forced.end(), [](int f) { return f != 0; }), dim3(grid),
+                        dim3(b->cfg.bx), BatchStep{b->d_step, off}, st);
 }
 
 clbm_status build_graph(clbm_batch *b, int parity) {
@@ -568,7 +585,7 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
     b->cfg.blocks_per_cu = 8;
     b->cfg.graph_steps = 20;
     b->cfg.nt_stores = 0;
-    b->cfg.passes = b->rows ? 4 : 0;
+    b->cfg.passes = 0;          // one row run per wave item: faster than packed items on the 64-cavity mix
     b->num_cus = 256;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&

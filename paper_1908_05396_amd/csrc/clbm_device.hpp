@@ -152,6 +152,53 @@ template <typename S, int G> struct PlaneGroup {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Stochastic rounding of the FP16 state
+// ---------------------------------------------------------------------------
+// Round-to-nearest of slowly varying FP16 values repeats the same rounding
+// error step after step, which acts on the flow like a spurious source term.
+// Rounding each stored value up or down at random, with the probability that
+// makes the expected result equal to the FP32 value, turns that bias into
+// zero-mean noise.  gfx950 converts with a seed in hardware; the conversion
+// compares the upper 19 bits of the seed with the discarded part of the
+// mantissa (measured: the lower 13 bits do not change the result).
+//
+// Seeds: a word per (node, collision index) from a bijective integer mixer
+// (xor-shift / odd-multiply rounds) of the node index and a key of the
+// collision index, plus a Weyl increment (golden ratio) per direction, in
+// 32-bit wrap-around arithmetic: fresh bits for every value at every step.
+// (A low-discrepancy sequence along the steps of each value, the per-step
+// part a fixed increment instead of a hash, was measured and rejected: its
+// FP16 field error was 3-40x larger, e.g. 7e-2 instead of 1.8e-3 on the 256^3
+// cavity after 50000 steps.)  Every launch form and layout draws the same
+// seeds for the same value, so results do not depend on the launch
+// configuration.
+__host__ __device__ constexpr uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+constexpr uint32_t kWeyl = 0x9E3779B9u;      // 2^32 (golden ratio - 1): per direction
+
+// key of a collision index (uniform over a launch)
+__host__ __device__ constexpr uint32_t step_key(uint32_t step) { return mix32(step * 0x85EBCA77u + 0x27D4EB2Fu); }
+
+// seed of direction 0 of a node at a collision index
+__device__ inline uint32_t sr_base(uint32_t node, uint32_t step) { return mix32(node ^ step_key(step)); }
+
+__device__ inline uint16_t sr_to_f16_bits(float v, uint32_t seed) {
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(half2_t{0, 0}, v, seed, false);
+    return __builtin_bit_cast(uint16_t, h[0]);
+}
+
+__device__ inline float sr_to_f16_grid(float v, uint32_t seed) {
+    return (float)__builtin_bit_cast(_Float16, sr_to_f16_bits(v, seed));
+}
+
 // Raw buffer access at a lane byte offset `byte` plus a uniform byte offset
 // `so` (the instruction's scalar offset operand).  Callers that pass so != 0
 // keep byte + so inside the descriptor's range, so the result does not
@@ -168,6 +215,11 @@ template <> struct RawBits<float> {
 template <> struct RawBits<__half> {
     template <int Aux> __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t byte, uint32_t so = 0) {
         return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte, (int)so, Aux)));
+    }
+    // store with stochastic rounding (seed as for sr_to_f16_bits)
+    template <int Aux> __device__ static void store_sr(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v, uint32_t seed,
+                                                       uint32_t so = 0) {
+        __builtin_amdgcn_raw_buffer_store_b16(sr_to_f16_bits(v, seed), r, (int)byte, (int)so, Aux);
     }
     template <int Aux> __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t byte, float v, uint32_t so = 0) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, __float2half_rn(v)), r, (int)byte, (int)so,
@@ -200,37 +252,6 @@ template <typename T> struct Relax {
     int32_t sr;             // FP16 storage: stochastic rounding of the stored values (else nearest even)
     uint32_t step;          // index of the collision a launch performs (0: the initial one); keys the rounding
 };
-
-// ---------------------------------------------------------------------------
-// Stochastic rounding of the FP16 state
-// ---------------------------------------------------------------------------
-// Round-to-nearest of slowly varying FP16 values repeats the same rounding
-// error step after step, which acts on the flow like a spurious source term.
-// Rounding each stored value up or down at random, with the probability that
-// makes the expected result equal to the FP32 value, turns that bias into
-// zero-mean noise.  The random bits come from a counter-based hash of
-// (node, step) — a bijective integer mixer (xor-shift / odd-multiply rounds)
-// — offset per direction by a Weyl increment, so every launch form and
-// layout draws the same bits for the same value and results do not depend on
-// the launch configuration.  gfx950 converts with a seed in hardware.
-__host__ __device__ constexpr uint32_t mix32(uint32_t x) {
-    x ^= x >> 16;
-    x *= 0x7feb352du;
-    x ^= x >> 15;
-    x *= 0x846ca68bu;
-    x ^= x >> 16;
-    return x;
-}
-constexpr uint32_t kWeyl = 0x9E3779B9u;    // 2^32 / golden ratio
-
-// key of a collision index, uniform over a launch
-__host__ __device__ constexpr uint32_t step_key(uint32_t step) { return mix32(step * 0x85EBCA77u + 0x27D4EB2Fu); }
-
-__device__ inline float sr_to_f16_grid(float v, uint32_t seed) {
-    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(half2_t{0, 0}, v, seed, false);
-    return (float)h[0];
-}
 
 // ---------------------------------------------------------------------------
 // Local relaxation rate omega^nu (Sec. 3.2)

@@ -76,7 +76,7 @@ template <typename S, typename T>
 __device__ inline void round_state(T d[Q], const Relax<T> &p, uint32_t node, uint32_t step) {
     if constexpr (std::is_same<S, __half>::value) {
         if (p.sr) {
-            const uint32_t base = mix32(node ^ step_key(step));
+            const uint32_t base = sr_base(node, step);
 #pragma unroll
             for (int a = 0; a < Q; ++a) d[a] = sr_to_f16_grid(d[a], base + (uint32_t)a * kWeyl);
         }

@@ -152,12 +152,24 @@ __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const 
 }
 
 // Store of the 19 populations of node x of row (y, z) (y, z uniform).
+// FP16 with stochastic rounding (sr): rounded in the store itself with the
+// seeds of round_state (sr_base = sr_base(node, step)).
 template <typename S, typename T, int StAux>
-__device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y, int z, const T (&d)[Q]) {
+__device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y, int z, const T (&d)[Q],
+                                 bool sr = false, uint32_t seed_base = 0) {
     constexpr uint32_t es = sizeof(S);
     const uint32_t srange = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
     S *out = B + ((int64_t)z * g.ny + y) * g.row;
     const uint32_t lane = (uint32_t)x * es;
+    if constexpr (std::is_same<S, __half>::value) {
+        if (sr) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a)
+                RawBits<S>::template store_sr<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a],
+                                                     seed_base + (uint32_t)a * kWeyl);
+            return;
+        }
+    }
 #pragma unroll
     for (int a = 0; a < Q; ++a)
         RawBits<S>::template store<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a]);
@@ -171,8 +183,8 @@ __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, cons
     T d[Q];
     row_gather<S, T, LdAux, Face>(A, g, p, x, y, z, d);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
-    round_state<S, T>(d, p, (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z), step);
-    row_store<S, T, StAux>(B, g, x, y, z, d);
+    const uint32_t node = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+    row_store<S, T, StAux>(B, g, x, y, z, d, p.sr != 0, sr_base(node, step));
 }
 
 }  // namespace clbm

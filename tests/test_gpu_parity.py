@@ -413,8 +413,14 @@ def test_srt_single_collision_populations(clbm, storage, tol):
     assert err < tol
 
 
-@pytest.mark.parametrize("n", [0.5, 1.0, 1.5])
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+SRT_F16_XFAIL = pytest.mark.xfail(
+    strict=True, reason="BGK comparison model, n = 0.5, FP16 storage: 6.2e-3 normwise at 300 steps (measured); its "
+                        "near-wall relaxation rates close to the clip leave the higher moments undamped, which keeps "
+                        "the FP16 rounding noise; the paper's cascaded scheme meets 2e-3 on the same case")
+
+
+@pytest.mark.parametrize("storage,n", [(st, n) for st in ("f64", "f32") for n in (0.5, 1.0, 1.5)] +
+                         [pytest.param("f16", 0.5, marks=SRT_F16_XFAIL), ("f16", 1.0), ("f16", 1.5)])
 def test_srt_cavity16(clbm, n, storage):
     """16^3 cavity with the BGK model, perturbed start, 300 steps."""
     spec = W.cavity(16, 0.05, n, 100.0, name=f"srt_cavity16_n{n}").with_(model="srt")
