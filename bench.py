@@ -217,7 +217,7 @@ def roofline(storage, nodes, kernel_ms_per_step, workload, steps_per_launch, lay
 BATCH_WORKLOAD = "batch64_cavities_L32-96_n0.4-1.6_re50-1000"
 
 
-def batched(clbm, torch, W, storage, steps, spinup):
+def batched(clbm, torch, W, storage, steps, spinup, tune=True):
     """The 64-cavity batch: one persistent launch per step (graph-replayed,
     autotuned after an untimed spin-up from rest) against one launch per
     instance per step, both timed with events on the launch stream over
@@ -228,7 +228,7 @@ def batched(clbm, torch, W, storage, steps, spinup):
     b = clbm.Batch(specs, storage=storage)
     b.init_rest()
     b.step(spinup)
-    cfg, _ = b.autotune()
+    cfg = b.autotune()[0] if tune else b.get_config()
     out = {"workload": BATCH_WORKLOAD, "instances": len(specs), "nodes": nodes, "storage": storage,
            "steps": steps, "spinup_steps": spinup, "config": cfg}
     stream = torch.cuda.current_stream()
@@ -472,6 +472,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 64-cavity batch (its own JSON line; for profiling the batch kernel)")
+    ap.add_argument("--batch-no-tune", action="store_true",
+                    help="time the batch in its default launch configuration (no autotuner trials)")
     ap.add_argument("--stability", action="store_true",
                     help="instead of the benchmark: largest stable lid velocity of the 64^3 cavity, cascaded "
                          "scheme vs the single-relaxation-time comparison model")
@@ -514,7 +516,10 @@ def main():
         print(json.dumps(accuracy64(clbm, torch, W, args.accuracy64)), flush=True)
         return
     if args.batch_only:
-        print(json.dumps(batched(clbm, torch, W, "f32", args.batch_steps, args.spinup)), flush=True)
+        out = batched(clbm, torch, W, "f32", args.batch_steps, args.spinup, not args.batch_no_tune)
+        if not args.no_copy:
+            out["copy_gbs"] = copy_bandwidth(clbm, torch)     # the counters' calibration in the same run
+        print(json.dumps(out), flush=True)
         return
     if args.accuracy512:
         print(json.dumps(accuracy_run(clbm, torch, W.config_cavity512(), args.accuracy512, 1000)[0]), flush=True)
