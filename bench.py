@@ -49,7 +49,7 @@ BYTES_PER_LUP = {"f64": 304, "f32": 152, "f16": 76}   # 19 reads + 19 writes per
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1908_05396_amd", "csrc", f)
                   for f in ("clbm_device.hpp", "clbm_internal.hpp", "clbm_rows.hpp", "clbm_kernels.hip",
-                            "clbm_rows.hip", "clbm_fused.hip")]
+                            "clbm_rows.hip", "clbm_fused.hip", "clbm_batch.hip")]
 # the one-step kernel of each state layout
 STEP_KERNEL = {"rows": "stream_collide_rows", "planes": "stream_collide"}
 
@@ -111,12 +111,13 @@ def accuracy_vs(torch, runs, ref_key, U, L):
 # Two steps per launch (planes layout) for each storage type: the fastest
 # patch height, z chunk, tile order and store hint of a sweep at 512^3
 # (rows 8/12/16 x planes 4..32 x both orders x both hints).
-TWO_STEP = {"f32": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0},
+TWO_STEP = {"f32": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 32, "xcd_remap": 1, "nt_stores": 0},
             "f16": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0},
             "f64": {"fuse_steps": 2, "fuse_rows": 8, "fuse_planes": 32, "xcd_remap": 0, "nt_stores": 1}}
 # The faster form per storage type at 512^3: FP32 two steps per launch (it
-# moves ~0.55x the bytes of two one-step launches); FP16 storage, bound by its
-# arithmetic, and FP64 one step per launch in the row layout.
+# moves about 0.6 of the bytes of two one-step launches; 32-plane z chunks
+# measured 0.6% faster than 16 in the developed flow); FP16 storage, bound by
+# its arithmetic, and FP64 one step per launch in the row layout.
 BEST_FORM = {"f32": "two", "f16": "one", "f64": "one"}
 
 
@@ -664,7 +665,7 @@ def main():
         "accuracy": accuracy,
     }
     if not args.no_batch:
-        line["batched"] = batched(clbm, torch, W, "f32", args.batch_steps, spin)
+        line["batched"] = batched(clbm, torch, W, "f32", args.batch_steps, spin, not args.batch_no_tune)
     if not args.no_copy:
         line["copy_gbs"] = round(copy_bandwidth(clbm, torch), 1)
     if not args.no_cpu:

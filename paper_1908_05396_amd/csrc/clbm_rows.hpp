@@ -91,16 +91,18 @@ __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const 
     const int64_t r = (int64_t)z * g.ny + y;
     // Each direction reads a run of its source row through a base one value
     // before the run; the lane offset selects x - cx(a) + 1, wrapped on a
-    // periodic x axis.  Offsets stay within nx + 2 values of the base, and
-    // every address lies inside the buffer (x - cx(a) = -1 or nx reaches the
-    // neighbouring run of the same row group, which the x-face rule below
-    // replaces).
+    // periodic x axis.  Offsets stay within nx + 2 values of the base.  On a
+    // non-periodic x face the source column x - cx(a) = -1 or nx is a ghost,
+    // whose value the x-face rule below supplies: those lanes take an offset
+    // beyond the descriptor's range, so the load returns 0 without touching
+    // memory (and the cache line past the run is not fetched for them).
     // (the ranges pass through readfirstlane so that the compiler keeps the
     // descriptors in scalar registers)
     const uint32_t range = __builtin_amdgcn_readfirstlane((uint32_t)(g.nx + 2) * es);
+    constexpr uint32_t outside = 0x80000000u;
     const uint32_t o0 = (uint32_t)(x + 1) * es;
-    const uint32_t op = (g.px && x == 0) ? range - 2 * es : (uint32_t)x * es;      // cx = +1: source x - 1
-    const uint32_t om = (g.px && x == g.nx - 1) ? es : (uint32_t)(x + 2) * es;     // cx = -1: source x + 1
+    const uint32_t op = x == 0 ? (g.px ? range - 2 * es : outside) : (uint32_t)x * es;              // cx = +1
+    const uint32_t om = x == g.nx - 1 ? (g.px ? es : outside) : (uint32_t)(x + 2) * es;           // cx = -1
     auto lane_off = [&](int a) { return cx(a) == 1 ? op : (cx(a) == -1 ? om : o0); };
     auto run = [&](int a, int64_t row) {
         return row_rsrc(A + row * g.row + (int64_t)a * g.nx - 1, range);
