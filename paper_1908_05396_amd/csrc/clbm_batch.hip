@@ -32,6 +32,13 @@ template <typename T> struct BatchInst {
     uint32_t bytes;     // bytes of the instance's state (row layout, packed items)
 };
 
+// Row-layout work item of one wave: the 64-wide run from x0 of row `row`
+// (pair = 0), or the short tails from x0 of two inner rows `row` and
+// row + pair, one per half of the wave (tails of at most 32 values).
+struct alignas(16) RowItem {
+    int32_t inst, row, x0, pair;
+};
+
 // The collision index of a launch (it keys the stochastic rounding of FP16
 // storage) is *step_base + step_off: step_base is set on the stream before
 // each run of launches, step_off is the launch's place in that run, so that
@@ -82,27 +89,37 @@ __device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T>
 template <typename S, typename T, int Route, int StAux, bool AnyForced>
 __global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
-                  const int32_t *__restrict__ tile_inst, uint32_t ntiles, const uint32_t *__restrict__ step_base,
+                  const RowItem *__restrict__ items, uint32_t nitems, const uint32_t *__restrict__ step_base,
                   uint32_t step_off) {
     const uint32_t step = __builtin_amdgcn_readfirstlane(*step_base + step_off);
     const uint32_t waves = blockDim.x >> 6;
     const uint32_t w0 = blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63u);
-    for (uint32_t t = w0; t < ntiles; t += gridDim.x * waves) {
-        const int i = __builtin_amdgcn_readfirstlane(tile_inst[t]);
+    for (uint32_t t = w0; t < nitems; t += gridDim.x * waves) {
+        const int i = __builtin_amdgcn_readfirstlane(items[t].inst);
+        const uint32_t row = (uint32_t)__builtin_amdgcn_readfirstlane(items[t].row);
+        const int x0 = __builtin_amdgcn_readfirstlane(items[t].x0);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane(items[t].pair);
         const Geom g = inst[i].g;
         const int64_t base = inst[i].base;
-        const uint32_t local = t - inst[i].tile0;
-        const uint32_t chunks = inst[i].chunks;
-        const uint32_t row = local / chunks;
-        const int x = (int)((local - row * chunks) * 64u) + lane;
         const int y = (int)(row % (uint32_t)g.ny), z = (int)(row / (uint32_t)g.ny);
-        if (x >= g.nx) continue;
         const Relax<T> &p = inst[i].p;
-        if (AnyForced && inst[i].forced)
-            batch_row<S, T, true, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
-        else
-            batch_row<S, T, false, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
+        const bool forced = AnyForced && inst[i].forced;
+        if (k == 0) {
+            const int x = x0 + lane;
+            if (x >= g.nx) continue;
+            if (forced)
+                batch_row<S, T, true, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
+            else
+                batch_row<S, T, false, Route, StAux>(A + base, B + base, g, p, x, y, z, step);
+        } else {
+            const int x = x0 + (lane & 31);
+            if (x >= g.nx) continue;
+            if (forced)
+                row_step_pair<S, T, true, 0, StAux, Route>(A + base, B + base, g, p, x, y, z, k, lane >= 32, step);
+            else
+                row_step_pair<S, T, false, 0, StAux, Route>(A + base, B + base, g, p, x, y, z, k, lane >= 32, step);
+        }
     }
 }
 
@@ -240,11 +257,11 @@ static hipError_t launch_batch_h(const void *A, void *B, const void *inst, const
     }
     if (rows) {
         if (route == 0)
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
-                               s.off);
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 0, StAux, AF>), grid, block, 0, st, a, b, d,
+                               (const RowItem *)tiles, ntiles, s.base, s.off);
         else
-            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux, AF>), grid, block, 0, st, a, b, d, tiles, ntiles, s.base,
-                               s.off);
+            hipLaunchKernelGGL((batch_rows_kernel<S, T, 1, StAux, AF>), grid, block, 0, st, a, b, d,
+                               (const RowItem *)tiles, ntiles, s.base, s.off);
         return hipGetLastError();
     }
     if (route == 0)
@@ -319,8 +336,8 @@ struct clbm_batch {
     // device tables
     uint32_t *d_step;       // collision index before the current run of launches
     void *d_inst;
-    int32_t *d_tiles;
-    size_t tile_cap;
+    int32_t *d_tiles;       // tile list: instance per tile, or RowItem (4 values) per row item
+    size_t tile_cap;        // int32 values
     uint32_t ntiles;
     // reductions
     double *partials;
@@ -389,26 +406,63 @@ clbm_status upload_tables_t(clbm_batch *b, const std::vector<Relax<T>> &relax) {
             total += (uint64_t)d.chunks * (uint64_t)g.nz;
         } else if (b->rows) {
             d.chunks = (uint32_t)((g.nx + 63) / 64);
-            total += (uint64_t)d.chunks * (uint64_t)g.ny * (uint64_t)g.nz;
         } else {
             d.chunks = (uint32_t)((g.nxy + b->cfg.bx - 1) / b->cfg.bx);
             total += (uint64_t)d.chunks * (uint64_t)g.nz;
         }
     }
-    if (total > 0x7fffffffull) return fail(CLBM_EINVAL, "batch has more than 2^31 tiles");
-    tiles.resize(total);
-    for (int i = 0; i < b->count; ++i) {
-        const bool per_row = b->rows && b->cfg.passes == 0;
-        const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz * (per_row ? (uint64_t)b->geom[i].ny : 1u);
-        std::fill(tiles.begin() + inst[i].tile0, tiles.begin() + inst[i].tile0 + n, i);
+    const bool per_row = b->rows && b->cfg.passes == 0;
+    if (per_row) {
+        // row items in row order; the short tails (at most 32 values) of two
+        // consecutive inner rows share a wave, one per half
+        for (int i = 0; i < b->count; ++i) {
+            const Geom &g = b->geom[i];
+            const int32_t chunks = (int32_t)inst[i].chunks, tail = g.nx % 64;
+            const bool short_tail = tail != 0 && tail <= 32;
+            const int32_t x_tail = 64 * (chunks - 1);
+            int32_t pending = -1;
+            inst[i].tile0 = (uint32_t)(tiles.size() / 4);
+            auto push = [&](int32_t row, int32_t x0, int32_t pair) {
+                tiles.push_back(i);
+                tiles.push_back(row);
+                tiles.push_back(x0);
+                tiles.push_back(pair);
+            };
+            for (int32_t z = 0; z < g.nz; ++z)
+                for (int32_t y = 0; y < g.ny; ++y) {
+                    const int32_t row = y + g.ny * z;
+                    for (int32_t c = 0; c < (short_tail ? chunks - 1 : chunks); ++c) push(row, 64 * c, 0);
+                    if (!short_tail) continue;
+                    const bool inner = y > 0 && y < g.ny - 1 && z > 0 && z < g.nz - 1;
+                    if (!inner) {
+                        push(row, x_tail, 0);
+                    } else if (pending < 0) {
+                        pending = row;
+                    } else {
+                        push(pending, x_tail, row - pending);
+                        pending = -1;
+                    }
+                }
+            if (pending >= 0) push(pending, x_tail, 0);
+            if (tiles.size() / 4 > 0x1fffffffull) return fail(CLBM_EINVAL, "batch has more than 2^29 row items");
+        }
+        total = tiles.size() / 4;
+    } else {
+        if (total > 0x7fffffffull) return fail(CLBM_EINVAL, "batch has more than 2^31 tiles");
+        tiles.resize(total);
+        for (int i = 0; i < b->count; ++i) {
+            const uint64_t n = (uint64_t)inst[i].chunks * (uint64_t)b->geom[i].nz;
+            std::fill(tiles.begin() + inst[i].tile0, tiles.begin() + inst[i].tile0 + n, i);
+        }
     }
-    if (total > b->tile_cap) {
+    const size_t vals = tiles.size();
+    if (vals > b->tile_cap) {
         if (b->d_tiles) (void)hipFree(b->d_tiles);
         b->d_tiles = nullptr;
-        HIP_TRY(hipMalloc((void **)&b->d_tiles, sizeof(int32_t) * total), "batch: tile table");
-        b->tile_cap = total;
+        HIP_TRY(hipMalloc((void **)&b->d_tiles, sizeof(int32_t) * vals), "batch: tile table");
+        b->tile_cap = vals;
     }
-    HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice), "batch: tiles");
+    HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int32_t) * vals, hipMemcpyHostToDevice), "batch: tiles");
     HIP_TRY(hipMemcpy(b->d_inst, inst.data(), sizeof(BatchInst<T>) * b->count, hipMemcpyHostToDevice),
             "batch: descriptors");
     b->ntiles = (uint32_t)total;

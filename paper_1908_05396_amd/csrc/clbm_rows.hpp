@@ -82,11 +82,22 @@ inline RowLaunch row_launch(const Geom &g, int bx, int by, int remap) {
     return L;
 }
 
+// A wave may serve two rows r and r + k of one lattice as two halves (the
+// short tails of two rows in a batch): every run the second half reads or
+// writes lies k row groups after the first half's, the same byte distance D
+// for all 19 directions, so its lanes add D to their offsets (`Shift::lane`)
+// and every descriptor's range grows by D (`Shift::range`).
+struct Shift {
+    uint32_t lane;      // bytes added to this lane's offsets (0 or D)
+    uint32_t range;     // D: added to every descriptor's range (uniform)
+};
+
 // Pull of node x of row (y, z) with the wall rules into d; y and z uniform
-// over the wave; Face: the row lies on a y or z face.
-template <typename S, typename T, int LdAux, bool Face>
+// over the wave (or over each half, Pair); Face: the row lies on a y or z face.
+template <typename S, typename T, int LdAux, bool Face, bool Pair = false>
 __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
-                                  T (&d)[Q]) {
+                                  T (&d)[Q], Shift sh = Shift{0u, 0u}) {
+    static_assert(!(Pair && Face), "paired rows lie off the y and z faces");
     constexpr uint32_t es = sizeof(S);
     const int64_t r = (int64_t)z * g.ny + y;
     // Each direction reads a run of its source row through a base one value
@@ -98,20 +109,23 @@ __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const 
     // memory (and the cache line past the run is not fetched for them).
     // (the ranges pass through readfirstlane so that the compiler keeps the
     // descriptors in scalar registers)
-    const uint32_t range = __builtin_amdgcn_readfirstlane((uint32_t)(g.nx + 2) * es);
+    // (a second half's offsets, past D, stay outside too: D + (nx + 2) values < 2^31 bytes)
+    const uint32_t run_range = __builtin_amdgcn_readfirstlane((uint32_t)(g.nx + 2) * es);
+    const uint32_t range = Pair ? run_range + sh.range : run_range;
+    const uint32_t add = Pair ? sh.lane : 0u;
     constexpr uint32_t outside = 0x80000000u;
-    const uint32_t o0 = (uint32_t)(x + 1) * es;
-    const uint32_t op = x == 0 ? (g.px ? range - 2 * es : outside) : (uint32_t)x * es;              // cx = +1
-    const uint32_t om = x == g.nx - 1 ? (g.px ? es : outside) : (uint32_t)(x + 2) * es;           // cx = -1
+    const uint32_t o0 = (uint32_t)(x + 1) * es + add;
+    const uint32_t op = (x == 0 ? (g.px ? run_range - 2 * es : outside) : (uint32_t)x * es) + add;     // cx = +1
+    const uint32_t om = (x == g.nx - 1 ? (g.px ? es : outside) : (uint32_t)(x + 2) * es) + add;      // cx = -1
     auto lane_off = [&](int a) { return cx(a) == 1 ? op : (cx(a) == -1 ? om : o0); };
     auto run = [&](int a, int64_t row) {
         return row_rsrc(A + row * g.row + (int64_t)a * g.nx - 1, range);
     };
     // the node's own row group, for the bounce-back values (slot in the lane offset)
-    const __amdgpu_buffer_rsrc_t own_rsrc =
-        row_rsrc(A + r * g.row, __builtin_amdgcn_readfirstlane((uint32_t)Q * (uint32_t)g.nx * es));
+    const uint32_t own_range = __builtin_amdgcn_readfirstlane((uint32_t)Q * (uint32_t)g.nx * es);
+    const __amdgpu_buffer_rsrc_t own_rsrc = row_rsrc(A + r * g.row, Pair ? own_range + sh.range : own_range);
     auto own = [&](int a) {
-        return (T)RawBits<S>::template load<LdAux>(own_rsrc, (uint32_t)(opp(a) * g.nx + x) * es);
+        return (T)RawBits<S>::template load<LdAux>(own_rsrc, (uint32_t)(opp(a) * g.nx + x) * es + add);
     };
     if constexpr (!Face) {
 #pragma unroll
@@ -153,16 +167,18 @@ __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const 
     }
 }
 
-// Store of the 19 populations of node x of row (y, z) (y, z uniform).
-// FP16 with stochastic rounding (sr): rounded in the store itself with the
-// seeds of round_state (sr_base = sr_base(node, step)).
-template <typename S, typename T, int StAux>
+// Store of the 19 populations of node x of row (y, z) (y, z uniform; Pair:
+// the second half's lanes shifted as in row_gather).  FP16 with stochastic
+// rounding (sr): rounded in the store itself with the seeds of round_state
+// (sr_base = sr_base(node, step)).
+template <typename S, typename T, int StAux, bool Pair = false>
 __device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y, int z, const T (&d)[Q],
-                                 bool sr = false, uint32_t seed_base = 0) {
+                                 bool sr = false, uint32_t seed_base = 0, Shift sh = Shift{0u, 0u}) {
     constexpr uint32_t es = sizeof(S);
-    const uint32_t srange = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
+    const uint32_t run_range = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
+    const uint32_t srange = Pair ? run_range + sh.range : run_range;
     S *out = B + ((int64_t)z * g.ny + y) * g.row;
-    const uint32_t lane = (uint32_t)x * es;
+    const uint32_t lane = (uint32_t)x * es + (Pair ? sh.lane : 0u);
     if constexpr (std::is_same<S, __half>::value) {
         if (sr) {
 #pragma unroll
@@ -187,6 +203,21 @@ __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, cons
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
     const uint32_t node = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
     row_store<S, T, StAux>(B, g, x, y, z, d, p.sr != 0, sr_base(node, step));
+}
+
+// The same step for a wave serving two inner rows r = y + ny z (lanes with
+// hi false) and r + k (lanes with hi true), each lane at column x of its row.
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
+__device__ inline void row_step_pair(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p,
+                                     int x, int y, int z, uint32_t k, bool hi, uint32_t step) {
+    constexpr uint32_t es = sizeof(S);
+    const uint32_t D = k * (uint32_t)g.row * es;
+    const Shift sh{hi ? D : 0u, D};
+    T d[Q];
+    row_gather<S, T, LdAux, false, true>(A, g, p, x, y, z, d, sh);
+    collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
+    const uint32_t node = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z + (hi ? k : 0u));
+    row_store<S, T, StAux, true>(B, g, x, y, z, d, p.sr != 0, sr_base(node, step), sh);
 }
 
 }  // namespace clbm
