@@ -83,12 +83,14 @@ __device__ inline void round_state(T d[Q], const Relax<T> &p, uint32_t node, uin
     }
 }
 
-// Newton steps of the FP32 relaxation-rate solve per storage type: four reach
-// FP32 precision (relative tau error <= 4e-13 in exact arithmetic over n in
-// [0.4, 1.6], K over five decades, a over twelve); FP16 storage, whose
-// resolution is 2^-11, takes three (error <= 1.4e-6 on the same envelope).
-template <typename S> struct NewtonSteps { static constexpr int value = 4; };
-template <> struct NewtonSteps<__half> { static constexpr int value = 3; };
+// Newton steps of the FP32 relaxation-rate solve (FP32 and FP16 storage; FP64
+// storage iterates to convergence).  Three steps from the tau = 1 estimate
+// leave a relative tau error <= 1.4e-6 in exact arithmetic over n in
+// [0.4, 1.6], K over five decades and a over twelve, and in FP32 arithmetic
+// the solve's own rounding is as large: a fourth step changes tau only at
+// that level (emulated in FP32: max |dtau| 2.6e-5 vs 2.2e-5 at n = 0.4, the
+// same at n >= 0.9).
+template <typename S> struct NewtonSteps { static constexpr int value = 3; };
 hipError_t launch_macroscopic(int storage, const void *A, const uint8_t *flags, void *rho, void *u, bool out_f32,
                               const Geom &g, const double *F, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t st);
