@@ -345,8 +345,10 @@ const char *clbm_last_error(void);
  * layout (EINVAL otherwise).  Instance i occupies clbm_buffer_size bytes of
  * its params, rounded up to 256, at a 256-byte-aligned offset of each pool, in
  * instance order.  Row layout: each wave takes (instance, z layer, k passes
- * of 64 consecutive nodes) items, or (instance, row, run of 64 x) items;
- * planes: each workgroup takes (instance, z layer, run of bx nodes) tiles.
+ * of 64 consecutive nodes) items, or (instance, row, run of 64 x) items, the
+ * short tails (at most 32 values) of two inner rows of an instance sharing
+ * one wave, a 32-lane half each; planes: each workgroup takes (instance,
+ * z layer, run of bx nodes) tiles.
  * Row-layout instances hold less than 2 GiB of state each.
  * ------------------------------------------------------------------------ */
 typedef struct clbm_batch clbm_batch;
@@ -360,7 +362,8 @@ typedef struct {
     int32_t nt_stores;         /* 1: non-temporal (streaming) stores, 0: plain stores (default: the
                                   short runs of small lattices leave partial cache lines, which plain
                                   stores let the cache merge) */
-    int32_t passes;            /* row layout: 0 = each wave item is one row's run of 64 x (default);
+    int32_t passes;            /* row layout: 0 = each wave item is one row's run of 64 x, or the short
+                                  tails of two inner rows (default);
                                   k > 0 = each item is k passes of 64 consecutive nodes of a z layer
                                   (rows packed into whole waves: fewer idle lanes for narrow lattices,
                                   per-lane row addressing); planes layout: must be 0 */

@@ -163,10 +163,13 @@ __device__ inline void aa_odd_row(S *__restrict__ A, const Geom &g, const Relax<
     const uint32_t prange = __builtin_amdgcn_readfirstlane((uint32_t)(g.nx + 2) * es);
     const uint32_t srange = __builtin_amdgcn_readfirstlane((uint32_t)g.nx * es);
     const bool xl = x == 0, xr = x == g.nx - 1;
-    // pull offsets from the base one value before the run
+    // pull offsets from the base one value before the run; a ghost source
+    // column of a non-periodic x face (replaced below) takes an offset beyond
+    // the descriptor's range, so its load touches no memory
+    constexpr uint32_t outside = 0x80000000u;
     const uint32_t o0 = (uint32_t)(x + 1) * es;
-    const uint32_t op = (g.px && xl) ? prange - 2 * es : (uint32_t)x * es;       // cx = +1: source x - 1
-    const uint32_t om = (g.px && xr) ? es : (uint32_t)(x + 2) * es;              // cx = -1: source x + 1
+    const uint32_t op = xl ? (g.px ? prange - 2 * es : outside) : (uint32_t)x * es;       // cx = +1: source x - 1
+    const uint32_t om = xr ? (g.px ? es : outside) : (uint32_t)(x + 2) * es;              // cx = -1: source x + 1
     // push offsets from the run start (kept inside the run on the lanes that skip the store)
     const uint32_t t0 = (uint32_t)x * es;
     const uint32_t tp = xr ? (g.px ? 0u : t0) : (uint32_t)(x + 1) * es;          // cx = +1: target x + 1
