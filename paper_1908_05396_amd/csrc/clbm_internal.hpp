@@ -77,8 +77,15 @@ __device__ inline void round_state(T d[Q], const Relax<T> &p, uint32_t node, uin
     if constexpr (std::is_same<S, __half>::value) {
         if (p.sr) {
             const uint32_t base = sr_base(node, step);
+            // the conversion keeps the high half of its first operand: the
+            // previous direction's result serves (values as sr_to_f16_grid)
+            typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+            half2_t h = __builtin_bit_cast(half2_t, (float)d[0]);
 #pragma unroll
-            for (int a = 0; a < Q; ++a) d[a] = sr_to_f16_grid(d[a], base + (uint32_t)a * kWeyl);
+            for (int a = 0; a < Q; ++a) {
+                h = __builtin_amdgcn_cvt_sr_f16_f32(h, (float)d[a], base + (uint32_t)a * kWeyl, false);
+                d[a] = (T)(float)h[0];
+            }
         }
     }
 }

@@ -181,10 +181,18 @@ __device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y,
     const uint32_t lane = (uint32_t)x * es + (Pair ? sh.lane : 0u);
     if constexpr (std::is_same<S, __half>::value) {
         if (sr) {
+            // each conversion keeps the high half of its first operand: the
+            // previous direction's result (stored already) serves, so no
+            // register is cleared per value; the stored low halves are those
+            // of sr_to_f16_bits
+            typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+            half2_t h = __builtin_bit_cast(half2_t, (float)d[0]);
 #pragma unroll
-            for (int a = 0; a < Q; ++a)
-                RawBits<S>::template store_sr<StAux>(row_rsrc(out + (int64_t)a * g.nx, srange), lane, d[a],
-                                                     seed_base + (uint32_t)a * kWeyl);
+            for (int a = 0; a < Q; ++a) {
+                h = __builtin_amdgcn_cvt_sr_f16_f32(h, (float)d[a], seed_base + (uint32_t)a * kWeyl, false);
+                __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h[0]),
+                                                      row_rsrc(out + (int64_t)a * g.nx, srange), (int)lane, 0, StAux);
+            }
             return;
         }
     }
