@@ -173,12 +173,12 @@ def test_autotune_keeps_state_and_caches(clbm, tmp_path):
 
 
 @pytest.mark.parametrize("layout", ["rows", "planes"])
-def test_config4_batch_full_size(clbm, layout):
+def test_cavity_batch64_full_size(clbm, layout):
     """The 64-cavity batch (edges 32..96, n in [0.4, 1.6], Re in [50, 1000])
     at full size: the persistent graph-replayed launch agrees with one launch
     per instance, and every instance keeps its mass (closed cavities)."""
     specs = W.config_batch()
-    print(f"[gpu] config-4 batch {layout}", flush=True)
+    print(f"[gpu] 64-cavity batch {layout}", flush=True)
     b = clbm.Batch(specs, storage="f32", layout=layout)
     b.init_rest()
     r0 = b.reduce()
@@ -209,13 +209,13 @@ def _oracle_post_collision(spec, seed, eps, pt, k):
 
 
 @pytest.mark.parametrize("layout", ["rows", "planes"])
-def test_config4_light_cone(clbm, layout):
+def test_cavity_batch64_light_cone(clbm, layout):
     """The 64-cavity batch at full size in the tuned launch the benchmark times,
     from a perturbed start: sampled nodes of six instances (lid corner, x face,
     interior, bottom wall) against the oracle after k steps."""
     specs = W.config_batch()
     k, eps, seed0 = 6, 2e-3, 500
-    print(f"[gpu] config-4 light cone {layout}", flush=True)
+    print(f"[gpu] 64-cavity batch light cone {layout}", flush=True)
     b = clbm.Batch(specs, storage="f32", layout=layout)
     b.init_rest()
     for i, sp in enumerate(specs):
