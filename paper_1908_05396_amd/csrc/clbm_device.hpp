@@ -272,7 +272,9 @@ template <typename T> struct Relax {
 template <typename T> struct NewtonTol;
 // FP32: four iterations from the tau = 1 estimate reach full precision over
 // n in [0.4, 1.6], K over five decades and a over twelve (checked against a
-// bisection reference); FP64 iterates to convergence.
+// bisection reference); they start the FP64 solve, which then iterates to
+// convergence.  The FP32 and FP16 storage kernels take three (NewtonSteps),
+// which already leave only the solve's own FP32 rounding.
 template <> struct NewtonTol<float> {
     static constexpr bool fixed = true;
     static constexpr int maxit = 4;
