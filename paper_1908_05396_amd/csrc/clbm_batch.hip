@@ -63,7 +63,7 @@ batch_step_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         if ((uint32_t)y * (uint32_t)g.nx > l) --y;
         if ((uint32_t)(y + 1) * (uint32_t)g.nx <= l) ++y;
         const int x = (int)(l - (uint32_t)y * (uint32_t)g.nx);
-        const Relax<T> &p = inst[i].p;
+        const Relax<T> p = inst[i].p;       // a copy: read once per item, not at each use
         const uint32_t self = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y + (uint32_t)g.nxy * (uint32_t)z;
         T d[Q];
         gather<S, T, 0>(A + base, g, p, x, y, z, self, d);
@@ -103,7 +103,7 @@ batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
         const Geom g = inst[i].g;
         const int64_t base = inst[i].base;
         const int y = (int)(row % (uint32_t)g.ny), z = (int)(row / (uint32_t)g.ny);
-        const Relax<T> &p = inst[i].p;
+        const Relax<T> p = inst[i].p;       // a copy: read once per item, not at each use
         const bool forced = AnyForced && inst[i].forced;
         if (k == 0) {
             const int x = x0 + lane;
@@ -225,7 +225,7 @@ batch_packed_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<
         const uint32_t chunks = inst[i].chunks;
         const int z = (int)(local / chunks);
         const uint32_t l0 = (local - (uint32_t)z * chunks) * passes * 64u;
-        const Relax<T> &p = inst[i].p;
+        const Relax<T> p = inst[i].p;       // a copy: read once per item, not at each use
         const uint32_t bytes = inst[i].bytes;
         const float inv_nx = inst[i].inv_nx;
         for (uint32_t j = 0; j < passes; ++j) {
