@@ -25,7 +25,7 @@ launch advances / average launch time measured with events on the launch
 stream, with the measured HBM traffic of the committed counter summary
 beside it), the other launch form and the planes layout of each storage
 type, the FP16-deviation and FP64 storage variants of the same workload, the
-64-cavity batch (persistent graph-replayed launch vs one launch per
+64-cavity batch (one graph-replayed launch per step vs one launch per
 instance, with its roofline), the achievable copy bandwidth, and the CPU
 oracle timed on the host cores on a bounded sample of the same workload.
 """
@@ -219,10 +219,10 @@ BATCH_WORKLOAD = "batch64_cavities_L32-96_n0.4-1.6_re50-1000"
 
 
 def batched(clbm, torch, W, storage, steps, spinup, tune=True):
-    """The 64-cavity batch: one persistent launch per step (graph-replayed,
+    """The 64-cavity batch: one launch per step for all instances (graph-replayed,
     autotuned after an untimed spin-up from rest) against one launch per
     instance per step, both timed with events on the launch stream over
-    `steps` steps; the roofline of the persistent kernel in algorithmic bytes
+    `steps` steps; the roofline of the batch kernel in algorithmic bytes
     per node update."""
     specs = W.config_batch()
     nodes = sum(s.nodes for s in specs)

@@ -339,8 +339,9 @@ const char *clbm_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent lattices (uneven sizes, Re, n, lids, forces)
- * advanced together, one persistent launch per time step whose workgroups
- * stride over the tiles of all instances; k steps are captured into a
+ * advanced together, one launch per time step whose workgroups stride over
+ * the tiles of all instances (a persistent grid of a few workgroups per CU,
+ * or up to one tile per wave: blocks_per_cu); k steps are captured into a
  * hipGraph and replayed.  All instances share the storage type and the
  * layout (EINVAL otherwise).  Instance i occupies clbm_buffer_size bytes of
  * its params, rounded up to 256, at a 256-byte-aligned offset of each pool, in
@@ -354,10 +355,14 @@ const char *clbm_last_error(void);
 typedef struct clbm_batch clbm_batch;
 
 typedef struct {
-    int32_t bx, by;            /* threads per workgroup, a multiple of 64, <= 512 (<= 256 for FP64);
+    int32_t bx, by;            /* threads per workgroup, a multiple of 64, <= 512 (<= 256 for FP64;
+                                  default: that maximum);
                                   planes: the tile is bx consecutive nodes of one z layer (x fastest);
                                   rows: bx / 64 waves, each on its own items; by must be 1 */
-    int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu x 256 workgroups (1..64) */
+    int32_t blocks_per_cu;     /* grid = blocks_per_cu x CUs workgroups (1..1024), at most one item
+                                  per wave; the workgroups stride over the item list (default 1024:
+                                  one item per wave on any batch, so that the dispatcher balances
+                                  the uneven item costs) */
     int32_t graph_steps;       /* steps per captured graph (0: plain launches) */
     int32_t nt_stores;         /* 1: non-temporal (streaming) stores, 0: plain stores (default: the
                                   short runs of small lattices leave partial cache lines, which plain
@@ -389,7 +394,7 @@ clbm_status clbm_batch_init_rest(clbm_batch *b, void *stream);
 clbm_status clbm_batch_init_populations(clbm_batch *b, int32_t i, const double *f0, int on_device, void *stream);
 
 /* Advance every instance by nsteps (the time step of clbm_step, Sec. 3):
- * one persistent launch per step over all tiles, replayed from captured
+ * one launch per step over all tiles, replayed from captured
  * graphs in chunks of graph_steps.  Asynchronous; the first call for a
  * graph length and buffer parity instantiates its graph. */
 clbm_status clbm_batch_step(clbm_batch *b, int64_t nsteps, void *stream);

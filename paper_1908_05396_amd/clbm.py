@@ -403,7 +403,7 @@ class Lattice:
 
 class Batch:
     """Many lattices (one problem description each, shared storage type)
-    stepped together by the batched persistent launch."""
+    stepped together, one batched launch per step."""
 
     def __init__(self, specs, storage: str = "f32", device="cuda", track_residual: bool = False,
                  tune_cache: str = None, collision: str = "auto", layout: str = "rows",

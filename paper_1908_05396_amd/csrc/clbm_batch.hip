@@ -1,8 +1,12 @@
 // Batched stepping of many independent lattices (declared in clbm.h).
 //
 // Every instance keeps its own geometry, power-law parameters, lid and
-// force; all share the storage type and the state layout.  One persistent
-// launch per time step covers the tiles of all instances.  Planes layout:
+// force; all share the storage type and the state layout.  One launch per
+// time step covers the tiles of all instances, its workgroups striding over
+// them; the grid runs from a persistent few workgroups per CU up to one tile
+// per wave (the autotuner's choice, and the default: the hardware dispatcher
+// then balances the uneven item costs, which a persistent grid leaves to the
+// slowest wave of each workgroup).  Planes layout:
 // workgroup b processes tiles b, b + G, b + 2G, ... of a flattened tile list,
 // each tile being (instance, z layer, run of bx consecutive nodes of that
 // layer in x-fastest order), so small lattices leave no lanes idle except at
@@ -375,7 +379,7 @@ clbm_status check_config(const clbm_batch *b, const clbm_batch_config *c) {
     const int mt = max_threads(b);
     if (c->bx < 64 || c->by != 1 || c->bx > mt || c->bx % 64 != 0)
         return fail(CLBM_EINVAL, "batch tile %d x %d: need by = 1 and bx a multiple of 64, <= %d", c->bx, c->by, mt);
-    if (c->blocks_per_cu < 1 || c->blocks_per_cu > 64) return fail(CLBM_EINVAL, "blocks_per_cu must lie in 1..64");
+    if (c->blocks_per_cu < 1 || c->blocks_per_cu > 1024) return fail(CLBM_EINVAL, "blocks_per_cu must lie in 1..1024");
     if (c->graph_steps < 0 || c->graph_steps > 4096) return fail(CLBM_EINVAL, "graph_steps must lie in 0..4096");
     if (c->nt_stores != 0 && c->nt_stores != 1) return fail(CLBM_EINVAL, "nt_stores must be 0 or 1");
     if (c->passes < 0 || c->passes > 256) return fail(CLBM_EINVAL, "passes must lie in 0..256");
@@ -634,9 +638,9 @@ clbm_status clbm_batch_create(const clbm_params *inst, int32_t count, void *pool
     b->pool[0] = pool_a;
     b->pool[1] = pool_b;
     b->bytes_each = bytes_each;
-    b->cfg.bx = 256;
+    b->cfg.bx = max_threads(b);
     b->cfg.by = 1;
-    b->cfg.blocks_per_cu = 8;
+    b->cfg.blocks_per_cu = 1024;    // capped at one item per wave (row layout) or one tile per workgroup
     b->cfg.graph_steps = 20;
     b->cfg.nt_stores = 0;
     b->cfg.passes = 0;          // one row run per wave item: faster than packed items on the 64-cavity mix
@@ -891,7 +895,7 @@ clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *
     if (!b->initialized) return fail(CLBM_ESTATE, "autotune needs an initialised state");
     hipStream_t st = (hipStream_t)stream;
     static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
-    static const int bpcs[] = {2, 4, 8, 16};
+    static const int bpcs[] = {8, 32, 128, 1024};      // 1024: at most one item per wave on any batch
     const clbm_batch_config keep = b->cfg;
     clbm_batch_config win = keep;
     double win_ms = 1e300;

@@ -1,4 +1,4 @@
-"""Batched persistent stepping (many lattices in one launch per step, graph
+"""Batched stepping (many lattices in one launch per step, graph
 replay, autotuned tiles) against the oracle and against the one-launch-per-
 instance reference path."""
 import os
@@ -153,6 +153,32 @@ def test_store_hint_gives_same_bits(clbm, layout):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("layout", ["rows", "planes"])
+def test_grid_size_gives_same_bits(clbm, layout):
+    """A persistent grid (one workgroup per CU, each wave striding over many
+    items), a mid-size one and the default (at most one item per wave) write
+    the same values; the configuration rejects grids outside 1..1024
+    workgroups per CU."""
+    specs = _mixed_specs()
+    outs = []
+    for bpc in (1024, 1, 3):
+        b = clbm.Batch(specs, storage="f32", layout=layout)
+        b.init_rest()
+        for i, sp in enumerate(specs):
+            b.init_populations(i, W.perturbed_populations(sp, 5 + i, 1e-3, device="cuda"))
+        b.set_config(blocks_per_cu=bpc, graph_steps=4)
+        assert b.get_config()["blocks_per_cu"] == bpc
+        b.step(11)
+        outs.append([b.populations(i).cpu().numpy() for i in range(len(specs))])
+        for bad in (0, 1025):
+            with pytest.raises(clbm.ClbmError):
+                b.set_config(blocks_per_cu=bad)
+        b.close()
+    for other in outs[1:]:
+        for x, y in zip(outs[0], other):
+            assert np.array_equal(x, y)
+
+
 def test_autotune_keeps_state_and_caches(clbm, tmp_path):
     specs = _mixed_specs()
     cache = str(tmp_path / "tune.txt")
@@ -175,7 +201,7 @@ def test_autotune_keeps_state_and_caches(clbm, tmp_path):
 @pytest.mark.parametrize("layout", ["rows", "planes"])
 def test_cavity_batch64_full_size(clbm, layout):
     """The 64-cavity batch (edges 32..96, n in [0.4, 1.6], Re in [50, 1000])
-    at full size: the persistent graph-replayed launch agrees with one launch
+    at full size: the graph-replayed batch launch agrees with one launch
     per instance, and every instance keeps its mass (closed cavities)."""
     specs = W.config_batch()
     print(f"[gpu] 64-cavity batch {layout}", flush=True)

@@ -89,7 +89,7 @@ def test_zero_steps_change_nothing(clbm, form):
 
 @pytest.mark.parametrize("layout", ["rows", "planes"])
 def test_degenerate_instances_in_a_batch(clbm, layout):
-    """The same lattices as instances of one batch (persistent launch, graph
+    """The same lattices as instances of one batch (one launch per step, graph
     replay), beside an ordinary one."""
     specs = list(_specs().values()) + [W.cavity(12, 0.05, 0.9, 50.0, name="b12")]
     steps, eps = 6, 1e-2
