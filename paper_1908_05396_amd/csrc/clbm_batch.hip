@@ -105,7 +105,13 @@ batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T>
                   uint32_t step_off) {
     const uint32_t step = __builtin_amdgcn_readfirstlane(*step_base + step_off);
     const uint32_t waves = blockDim.x >> 6;
-    const uint32_t w0 = blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-contiguous order: workgroups wg, wg + 8, ... run on one XCD, so they
+    // take consecutive items, and the partial cache lines that neighbouring
+    // rows share meet in that XCD's L2
+    uint32_t wg = blockIdx.x;
+    const uint32_t aligned = gridDim.x & ~7u;
+    if (wg < aligned) wg = (wg & 7u) * (aligned >> 3) + (wg >> 3);
+    const uint32_t w0 = wg * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63u);
     for (uint32_t t = w0; t < nitems; t += gridDim.x * waves) {
         const int i = __builtin_amdgcn_readfirstlane(items[t].inst);
