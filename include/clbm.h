@@ -361,8 +361,8 @@ typedef struct {
                                   rows: bx / 64 waves, each on its own items; by must be 1 */
     int32_t blocks_per_cu;     /* grid = blocks_per_cu x CUs workgroups (1..1024), at most one item
                                   per wave; the workgroups stride over the item list (default 1024:
-                                  one item per wave on any batch, so that the dispatcher balances
-                                  the uneven item costs) */
+                                  one item per wave up to 1024 x CUs x bx/64 items, 2^21 on 256 CUs
+                                  at bx 512, so that the dispatcher balances the uneven item costs) */
     int32_t graph_steps;       /* steps per captured graph (0: plain launches) */
     int32_t nt_stores;         /* 1: non-temporal (streaming) stores, 0: plain stores (default: the
                                   short runs of small lattices leave partial cache lines, which plain

@@ -909,7 +909,7 @@ clbm_status clbm_batch_autotune(clbm_batch *b, void *stream, clbm_batch_config *
     if (!b->initialized) return fail(CLBM_ESTATE, "autotune needs an initialised state");
     hipStream_t st = (hipStream_t)stream;
     static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
-    static const int bpcs[] = {8, 32, 128, 1024};      // 1024: at most one item per wave on any batch
+    static const int bpcs[] = {8, 32, 128, 1024};      // 1024: one item per wave up to 2^21 items (2^20 at bx 256)
     const clbm_batch_config keep = b->cfg;
     clbm_batch_config win = keep;
     double win_ms = 1e300;
