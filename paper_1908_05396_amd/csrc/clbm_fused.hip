@@ -67,6 +67,26 @@ template <typename S, bool PF> struct LdsBytes { static constexpr int value = PF
 // s_waitcnt vmcnt(0) with the other counters left free (gfx9 encoding)
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// DPP controls of the whole-wave shifts by one lane (gfx9 encoding): lane l
+// reads lane l - 1 (shift right) or lane l + 1 (shift left)
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+// x neighbours of the e_y = 0 values held in registers: lane l takes lane
+// l - 1's value (from_left) or lane l + 1's (from_right); the end lanes get
+// values no output uses.  FP32 by a whole-wave DPP shift (one VALU move,
+// no LDS round trip), FP64 through the LDS permute.
+template <typename T> __device__ inline T from_left(T v) { return __shfl_up(v, 1, kLanes); }
+template <typename T> __device__ inline T from_right(T v) { return __shfl_down(v, 1, kLanes); }
+template <> __device__ inline float from_left<float>(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kDppWaveShr1, 0xF, 0xF,
+                                                                 false));
+}
+template <> __device__ inline float from_right<float>(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kDppWaveShl1, 0xF, 0xF,
+                                                                 false));
+}
+
 template <typename S, typename T> __device__ inline T round_trip(T v) {
     return Conv<S, T>::load(Conv<S, T>::store(v));
 }
@@ -192,9 +212,9 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
     // second step at output plane z (jz = z - z0 + 1 indexes I(z))
     auto second_step = [&](int z, int jz) {
         // every lane takes part in the shuffles; lanes 1..62 use them
-        const T n1 = __shfl_up(r0c[1], 1, kLanes), n2 = __shfl_down(r0c[2], 1, kLanes);
-        const T n11 = __shfl_up(rpp[1], 1, kLanes), n12 = __shfl_down(rpp[2], 1, kLanes);
-        const T n13 = __shfl_up(rmn[1], 1, kLanes), n14 = __shfl_down(rmn[2], 1, kLanes);
+        const T n1 = from_left(r0c[1]), n2 = from_right(r0c[2]);
+        const T n11 = from_left(rpp[1]), n12 = from_right(rpp[2]);
+        const T n13 = from_left(rmn[1]), n14 = from_right(rmn[2]);
         if (!out) return;
         T d[Q];
         d[0] = r0c[0]; d[1] = n1; d[2] = n2;
