@@ -176,9 +176,9 @@ stream_collide2_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, Relax
             if constexpr (Rows) {
                 // the wave's row (wy, wz) is uniform: off the y and z faces, or on one
                 if (wy >= 1 && wy <= g.ny - 2 && wz >= 1 && wz <= g.nz - 2)
-                    row_gather<S, T, 0, false>(A, g, p, wx, wy, wz, d);
+                    row_gather<S, T, 0, false, false, XGroupRows<S>::value>(A, g, p, wx, wy, wz, d);
                 else
-                    row_gather<S, T, 0, true>(A, g, p, wx, wy, wz, d);
+                    row_gather<S, T, 0, true, false, XGroupRows<S>::value>(A, g, p, wx, wy, wz, d);
             } else if constexpr (PF) {
 #pragma unroll
                 for (int a = 0; a < Q; ++a) d[a] = Conv<S, T>::load(pf.in[a][w][l]);

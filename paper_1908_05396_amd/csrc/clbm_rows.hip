@@ -62,7 +62,7 @@ stream_collide_rows_kernel(const S *__restrict__ A, S *__restrict__ B, Geom g, R
     if (!row_of(R, x, ri) || x >= g.nx) return;
     int y, z;
     inner_row(g, ri, y, z);
-    row_step<S, T, Forced, LdAux, StAux, Route, false>(A, B, g, p, x, y, z, p.step);
+    row_step<S, T, Forced, LdAux, StAux, Route, false, XGroupRows<S>::value>(A, B, g, p, x, y, z, p.step);
 }
 
 template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route>
@@ -73,7 +73,7 @@ stream_collide_rows_face_kernel(const S *__restrict__ A, S *__restrict__ B, Geom
     if (!row_of(R, x, ri) || x >= g.nx) return;
     int y, z;
     face_row(g, R, ri, y, z);
-    row_step<S, T, Forced, LdAux, StAux, Route, true>(A, B, g, p, x, y, z, p.step);
+    row_step<S, T, Forced, LdAux, StAux, Route, true, XGroupRows<S>::value>(A, B, g, p, x, y, z, p.step);
 }
 
 template <typename S, typename T, bool Forced, int Route>

@@ -87,14 +87,21 @@ inline RowLaunch row_launch(const Geom &g, int bx, int by, int remap) {
 // writes lies k row groups after the first half's, the same byte distance D
 // for all 19 directions, so its lanes add D to their offsets (`Shift::lane`)
 // and every descriptor's range grows by D (`Shift::range`).
+// Single-lattice row kernels group the x-face bounce-back loads of a wave
+// (row_gather's XGroup) with FP32 storage: at 512^3 the one-step launch runs
+// 1.3% and the two-step one 2.9% faster, while FP16 storage (bound by its
+// arithmetic) and the batch (every wave holding face lanes) ran 3-4% slower.
+template <typename S> struct XGroupRows { static constexpr bool value = std::is_same<S, float>::value; };
+
 struct Shift {
     uint32_t lane;      // bytes added to this lane's offsets (0 or D)
     uint32_t range;     // D: added to every descriptor's range (uniform)
 };
 
 // Pull of node x of row (y, z) with the wall rules into d; y and z uniform
-// over the wave (or over each half, Pair); Face: the row lies on a y or z face.
-template <typename S, typename T, int LdAux, bool Face, bool Pair = false>
+// over the wave (or over each half, Pair); Face: the row lies on a y or z face;
+// XGroup: the x-face bounce-back loads of a wave issued together (below).
+template <typename S, typename T, int LdAux, bool Face, bool Pair = false, bool XGroup = false>
 __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const Relax<T> &p, int x, int y, int z,
                                   T (&d)[Q], Shift sh = Shift{0u, 0u}) {
     static_assert(!(Pair && Face), "paired rows lie off the y and z faces");
@@ -154,15 +161,45 @@ __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const 
         }
     }
     // lanes on a non-periodic x face: directions whose source row is inside
-    // the lattice but whose source column is a ghost
-    if (!g.px && (x == 0 || x == g.nx - 1)) {
+    // the lattice but whose source column is a ghost take the bounce-back of
+    // the node's own opposite population (XGroup: the wave issues these loads
+    // all together, the lanes without such a ghost taking an out-of-range
+    // offset, i.e. no memory access, and selects the wall values afterwards,
+    // so that it waits for memory once instead of once per direction; that
+    // pays where the waves of a row rarely hold face lanes and their
+    // arithmetic leaves issue slots free: FP32 storage on large lattices)
+    if constexpr (!XGroup) {
+        if (!g.px && (x == 0 || x == g.nx - 1)) {
 #pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            if (cx(a) == 0 || !((x == 0 && cx(a) == 1) || (x == g.nx - 1 && cx(a) == -1))) continue;
-            const int sy = y - cy(a), sz = z - cz(a);
-            const bool row_wall = (!g.py && (sy < 0 || sy >= g.ny)) || (!g.pz && (sz < 0 || sz >= g.nz));
-            if (row_wall) continue;     // bounced back above, with the lid term of every ghost coordinate
-            d[a] = wall_value<T>(own(a), p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
+            for (int a = 1; a < Q; ++a) {
+                if (cx(a) == 0 || !((x == 0 && cx(a) == 1) || (x == g.nx - 1 && cx(a) == -1))) continue;
+                const int sy = y - cy(a), sz = z - cz(a);
+                const bool row_wall = (!g.py && (sy < 0 || sy >= g.ny)) || (!g.pz && (sz < 0 || sz >= g.nz));
+                if (row_wall) continue;     // bounced back above, with the lid term of every ghost coordinate
+                d[a] = wall_value<T>(own(a), p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
+            }
+        }
+    } else if (!g.px) {
+        const bool lo = x == 0, hi = x == g.nx - 1;
+        if (__builtin_amdgcn_ballot_w64(lo || hi) != 0) {       // uniform over the wave
+            T o[Q];
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                if (cx(a) == 0) continue;
+                const bool ghost = cx(a) == 1 ? lo : hi;
+                o[a] = (T)RawBits<S>::template load<LdAux>(
+                    own_rsrc, ghost ? (uint32_t)(opp(a) * g.nx + x) * es + add : outside);
+            }
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                if (cx(a) == 0) continue;
+                const int sy = y - cy(a), sz = z - cz(a);
+                const bool row_wall = (!g.py && (sy < 0 || sy >= g.ny)) || (!g.pz && (sz < 0 || sz >= g.nz));
+                if (row_wall) continue;     // bounced back above, with the lid term of every ghost coordinate
+                const bool ghost = cx(a) == 1 ? lo : hi;
+                const T w = wall_value<T>(o[a], p, a, (g.lid_mask & (cx(a) == 1 ? 1 : 2)) != 0);
+                d[a] = ghost ? w : d[a];
+            }
         }
     }
 }
@@ -203,11 +240,11 @@ __device__ inline void row_store(S *__restrict__ B, const Geom &g, int x, int y,
 
 // One step of node x of row (y, z): gather, collide, store; `step` is the
 // index of the collision (keys the stochastic rounding of FP16 storage).
-template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face>
+template <typename S, typename T, bool Forced, int LdAux, int StAux, int Route, bool Face, bool XGroup = false>
 __device__ inline void row_step(const S *__restrict__ A, S *__restrict__ B, const Geom &g, const Relax<T> &p, int x,
                                 int y, int z, uint32_t step) {
     T d[Q];
-    row_gather<S, T, LdAux, Face>(A, g, p, x, y, z, d);
+    row_gather<S, T, LdAux, Face, false, XGroup>(A, g, p, x, y, z, d);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
     const uint32_t node = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
     row_store<S, T, StAux>(B, g, x, y, z, d, p.sr != 0, sr_base(node, step));
