@@ -10,8 +10,8 @@ shear and skip the relaxation-rate solve, so steps timed near rest would be
 faster than the developed flow of the 5000-step run.  The first --rest-steps
 of the main run's spin-up are timed on their own and reported as a secondary
 figure.  Each storage type runs in its faster launch form: FP32 two steps per
-launch (temporal blocking, planes layout; one launch = two full steps of the
-fused pull stream-collide), FP16 deviations (stochastic rounding) and FP64
+launch (temporal blocking in the row-interleaved layout; one launch = two
+full steps of the fused pull stream-collide), FP16 deviations (stochastic rounding) and FP64
 one step per launch in the row-interleaved layout (a launch for the rows off
 the y and z faces and one for the face rows).  All storage types run the same
 spin-up, warm-up and timed steps, and the errors of FP32 and FP16 against FP64
@@ -108,16 +108,18 @@ def accuracy_vs(torch, runs, ref_key, U, L):
     return out
 
 
-# Two steps per launch (planes layout) for each storage type: the fastest
-# patch height, z chunk, tile order and store hint of a sweep at 512^3
-# (rows 8/12/16 x planes 4..32 x both orders x both hints).
-TWO_STEP = {"f32": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 32, "xcd_remap": 1, "nt_stores": 0},
+# Two steps per launch for each storage type: the fastest layout, patch
+# height, z chunk, tile order and store hint of a sweep at 512^3 (rows
+# 8/12/16 x planes 4..48 x both orders x both hints x both layouts).  FP32 in
+# the row layout with 16-plane chunks: 3.156 ms per step against 3.238 in the
+# planes layout with 32-plane chunks, the better one there.
+TWO_STEP = {"f32": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0},
             "f16": {"fuse_steps": 2, "fuse_rows": 16, "fuse_planes": 16, "xcd_remap": 1, "nt_stores": 0},
             "f64": {"fuse_steps": 2, "fuse_rows": 8, "fuse_planes": 32, "xcd_remap": 0, "nt_stores": 1}}
+TWO_STEP_LAYOUT = {"f32": "rows", "f16": "planes", "f64": "planes"}
 # The faster form per storage type at 512^3: FP32 two steps per launch (it
-# moves about 0.6 of the bytes of two one-step launches; 32-plane z chunks
-# measured 0.6% faster than 16 in the developed flow); FP16 storage, bound by
-# its arithmetic, and FP64 one step per launch in the row layout.
+# moves about 0.6 of the bytes of two one-step launches); FP16 storage, bound
+# by its arithmetic, and FP64 one step per launch in the row layout.
 BEST_FORM = {"f32": "two", "f16": "one", "f64": "one"}
 
 
@@ -136,7 +138,7 @@ def time_lattice(clbm, torch, spec, storage, steps, warmup, reduce_every, block=
     timed on their own: the near-rest transient), `warmup` untimed steps, and
     `steps` timed steps; returns timing and reduction results (and the final
     velocity field, FP64 on the device, if `keep_u`).  `launch`: a launch
-    dict (two steps per launch need the planes layout) or None."""
+    dict or None (the library default)."""
     lat = clbm.Lattice(spec, storage=storage, track_residual=False, block=block, in_place=in_place, launch=launch,
                        layout=layout)
     lat.init_rest()
@@ -537,7 +539,8 @@ def main():
     def run_form(st, form, steps, warmup, keep_u=False, rest_steps=0):
         launch = launch_of(form, st, spec)
         return time_lattice(clbm, torch, spec, st, steps, warmup, args.reduce_every, keep_u=keep_u, launch=launch,
-                            layout="planes" if launch else args.layout, spinup=spin, rest_steps=rest_steps)
+                            layout=TWO_STEP_LAYOUT[st] if launch else args.layout, spinup=spin,
+                            rest_steps=rest_steps)
 
     def frac_of(st, ms):
         return round(BYTES_PER_LUP[st] * spec.nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)

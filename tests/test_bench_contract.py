@@ -19,7 +19,7 @@ WORKLOAD = "cavity512_re3200_n0.75"
 
 def test_roofline_object():
     n = 512 ** 3
-    for storage, spl, layout in (("f32", 2, "planes"), ("f16", 1, "rows"), ("f64", 1, "rows")):
+    for storage, spl, layout in (("f32", 2, "rows"), ("f16", 1, "rows"), ("f64", 1, "rows")):
         r = bench.roofline(storage, n, 3.0, WORKLOAD, spl, layout)
         for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
             assert k in r
@@ -37,6 +37,7 @@ def test_launch_forms():
             assert c["fuse_steps"] == 2
             assert c["fuse_rows"] in ((8,) if storage == "f64" else (8, 12, 16))
             assert c["xcd_remap"] in (0, 1) and c["nt_stores"] in (0, 1) and c["fuse_planes"] >= 1
+            assert bench.TWO_STEP_LAYOUT[storage] in ("rows", "planes")
         else:
             assert c is None
     short = type("S", (), {"nz": 5})()
