@@ -82,17 +82,17 @@ inline RowLaunch row_launch(const Geom &g, int bx, int by, int remap) {
     return L;
 }
 
-// A wave may serve two rows r and r + k of one lattice as two halves (the
-// short tails of two rows in a batch): every run the second half reads or
-// writes lies k row groups after the first half's, the same byte distance D
-// for all 19 directions, so its lanes add D to their offsets (`Shift::lane`)
-// and every descriptor's range grows by D (`Shift::range`).
 // Single-lattice row kernels group the x-face bounce-back loads of a wave
 // (row_gather's XGroup) with FP32 storage: at 512^3 the one-step launch runs
 // 1.3% and the two-step one 2.9% faster, while FP16 storage (bound by its
 // arithmetic) and the batch (every wave holding face lanes) ran 3-4% slower.
 template <typename S> struct XGroupRows { static constexpr bool value = std::is_same<S, float>::value; };
 
+// A wave may serve two rows r and r + k of one lattice as two halves (the
+// short tails of two rows in a batch): every run the second half reads or
+// writes lies k row groups after the first half's, the same byte distance D
+// for all 19 directions, so its lanes add D to their offsets (`Shift::lane`)
+// and every descriptor's range grows by D (`Shift::range`).
 struct Shift {
     uint32_t lane;      // bytes added to this lane's offsets (0 or D)
     uint32_t range;     // D: added to every descriptor's range (uniform)
