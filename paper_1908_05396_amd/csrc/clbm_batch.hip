@@ -85,21 +85,13 @@ template <typename S, typename T, bool Forced, int Route, int StAux>
 __device__ inline void batch_row(const S *A, S *B, const Geom &g, const Relax<T> &p, int x, int y, int z,
                                  uint32_t step) {
     if (y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1)
-        row_step<S, T, Forced, 0, StAux, Route, true>(A, B, g, p, x, y, z, step);
+        row_step<S, T, Forced, 0, StAux, Route, true, XGroupRows<S>::value>(A, B, g, p, x, y, z, step);
     else
-        row_step<S, T, Forced, 0, StAux, Route, false>(A, B, g, p, x, y, z, step);
+        row_step<S, T, Forced, 0, StAux, Route, false, XGroupRows<S>::value>(A, B, g, p, x, y, z, step);
 }
 
-// Waves per SIMD the row kernel is compiled for: eight for the unforced
-// central-moment collision in FP32 arithmetic, which then fits 78 scalar
-// registers without spilling (more waves in flight over the short runs, each
-// wave taking about one item); as many as the registers allow otherwise.
-template <typename T, int Route, bool AnyForced> struct BatchRowWaves {
-    static constexpr int value = (std::is_same<T, float>::value && Route == 0 && !AnyForced) ? 8 : 1;
-};
-
 template <typename S, typename T, int Route, int StAux, bool AnyForced>
-__global__ void __launch_bounds__(MaxThreads<T>::value, (BatchRowWaves<T, Route, AnyForced>::value))
+__global__ void __launch_bounds__(MaxThreads<T>::value)
 batch_rows_kernel(const S *__restrict__ A, S *__restrict__ B, const BatchInst<T> *__restrict__ inst,
                   const RowItem *__restrict__ items, uint32_t nitems, const uint32_t *__restrict__ step_base,
                   uint32_t step_off) {

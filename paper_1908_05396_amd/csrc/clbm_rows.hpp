@@ -82,10 +82,12 @@ inline RowLaunch row_launch(const Geom &g, int bx, int by, int remap) {
     return L;
 }
 
-// Single-lattice row kernels group the x-face bounce-back loads of a wave
-// (row_gather's XGroup) with FP32 storage: at 512^3 the one-step launch runs
-// 1.3% and the two-step one 2.9% faster, while FP16 storage (bound by its
-// arithmetic) and the batch (every wave holding face lanes) ran 3-4% slower.
+// Row kernels group the x-face bounce-back loads of a wave (row_gather's
+// XGroup) with FP32 storage: at 512^3 the one-step launch runs 1.3% and the
+// two-step one 2.9% faster, the 64-cavity batch 2.8% (its waves all hold face
+// lanes; compiled at seven waves per SIMD, since the grouped loads need more
+// than the 64 VGPRs of eight).  FP16 storage, bound by its arithmetic, ran 3%
+// slower that way and keeps the per-direction path.
 template <typename S> struct XGroupRows { static constexpr bool value = std::is_same<S, float>::value; };
 
 // A wave may serve two rows r and r + k of one lattice as two halves (the
@@ -165,9 +167,7 @@ __device__ inline void row_gather(const S *__restrict__ A, const Geom &g, const 
     // the node's own opposite population (XGroup: the wave issues these loads
     // all together, the lanes without such a ghost taking an out-of-range
     // offset, i.e. no memory access, and selects the wall values afterwards,
-    // so that it waits for memory once instead of once per direction; that
-    // pays where the waves of a row rarely hold face lanes and their
-    // arithmetic leaves issue slots free: FP32 storage on large lattices)
+    // so that it waits for memory once instead of once per direction)
     if constexpr (!XGroup) {
         if (!g.px && (x == 0 || x == g.nx - 1)) {
 #pragma unroll
@@ -259,7 +259,7 @@ __device__ inline void row_step_pair(const S *__restrict__ A, S *__restrict__ B,
     const uint32_t D = k * (uint32_t)g.row * es;
     const Shift sh{hi ? D : 0u, D};
     T d[Q];
-    row_gather<S, T, LdAux, false, true>(A, g, p, x, y, z, d, sh);
+    row_gather<S, T, LdAux, false, true, XGroupRows<S>::value>(A, g, p, x, y, z, d, sh);
     collide<T, Forced, Route, NewtonSteps<S>::value>(d, p, nullptr);
     const uint32_t node = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z + (hi ? k : 0u));
     row_store<S, T, StAux, true>(B, g, x, y, z, d, p.sr != 0, sr_base(node, step), sh);
